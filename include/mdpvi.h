@@ -1,0 +1,165 @@
+/*
+ * mdpvi.h -- C ABI of the MI355X value-iteration library for the occupancy
+ * MDP of vehicular bag-of-task placement.
+ *
+ * The model (paper Sec. V-B..V-G): K vehicular clouds ("hosts") of C VM
+ * units each; J task classes, a class-j task needs size[j] units, arrives as
+ * a Poisson stream of rate lambda[j]; each occupied unit is released at
+ * rate mu; each host leaves at rate nu and is replaced empty (its VMs are
+ * dropped).  The state (Eq. (10)) is the occupancy vector n = (n_0..n_{K-1})
+ * together with the class e of the pending placement request; the actions
+ * (Eq. (11)) are "place on host a" (a = 0..K-1, feasible iff
+ * n_a + size[e] <= C) and "send to the paid cloud" (a = K, always
+ * feasible).  The continuous-time chain is uniformised at
+ *   Lam = sum_j lambda[j] + K*C*mu + K*nu,
+ * the reward (Eqs. (14)-(16)) is reward[e] for a placement and
+ * -reject_cost[e] for the paid cloud, paid on the arrival branch, and
+ * the Bellman equation (Eq. (18)) carries a discount gamma per uniformised
+ * step:
+ *   Q(s,a) = P_arr R(e,a) + gamma * sum_s' P(s'|s,a) V(s'),
+ *   V(s)   = max over feasible a of Q(s,a),    P_arr = sum_j lambda[j] / Lam.
+ *
+ * Layout of every per-state array (values, policies, gaps, adjoints):
+ *   index(n, e) = sum_k n_k (C+1)^k + e (C+1)^K     (host 0 fastest, class slowest)
+ *   N = J (C+1)^K entries.
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: MDPVI_OK (0) or a negative MDPVI_E* code; the message of
+ *     the last failure on the calling thread is mdpvi_last_error().  No C++
+ *     exception crosses this boundary.
+ *   - Array arguments marked "device" are caller-owned device pointers of
+ *     the GPU that is current when the call is made; the library never
+ *     frees or keeps them.  The library owns the handle and its scratch
+ *     (a second value buffer, residual slots, counters, pinned host words),
+ *     allocated on first use and freed by mdp_free.
+ *   - hip_stream is a hipStream_t (NULL = the null stream).  vi_solve,
+ *     policy_eval and vi_adjoint return only after the stream has reached
+ *     their stopping test (they must read the residual); policy_extract,
+ *     policy_extract_f64 and policy_greedy are asynchronous on the stream.
+ *   - One handle must not be used from two threads or on two streams at the
+ *     same time.  Distinct handles are independent.
+ */
+#ifndef MDPVI_H
+#define MDPVI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MDPVI_OK        0
+#define MDPVI_EINVAL   (-1)  /* invalid argument: parameter out of range, NULL pointer */
+#define MDPVI_ERANGE   (-2)  /* state space too large (N > 2^62) or size overflow      */
+#define MDPVI_ENOCONV  (-3)  /* max_iter reached before the stopping test passed;
+                                outputs and stats are valid (the last iterate)      */
+#define MDPVI_ENAN     (-4)  /* a NaN / Inf appeared in the iterate                  */
+#define MDPVI_EDEVICE  (-5)  /* a HIP runtime call failed (its text is in last_error) */
+#define MDPVI_ENOMEM   (-6)  /* device or pinned host allocation failed              */
+
+#define MDPVI_MAX_K 16       /* hosts */
+#define MDPVI_MAX_J 8        /* task classes */
+
+/* Model parameters (Sec. V-B..V-E).  All pointers are host pointers to J
+ * entries, read during mdp_build only.
+ *   K in [1, 16], C >= 1, J in [1, 8], 1 <= size[j] <= C,
+ *   lambda[j] >= 0 finite with sum > 0, mu >= 0, nu >= 0 finite,
+ *   reward[j] finite, reject_cost NULL (all 0) or finite entries,
+ *   gamma in [0, 1).                                                      */
+typedef struct {
+    int32_t K, C, J;
+    const int32_t *size;
+    const double *lambda;
+    double mu;
+    double nu;
+    const double *reward;
+    const double *reject_cost;
+    double gamma;
+} mdpvi_params;
+
+typedef struct mdpvi_mdp *mdpvi_mdp_t;
+
+/* Figures of one iterative call.  iterations = sweeps executed until the
+ * stopping test passed; residual_inf = ||V^k - V^{k-1}||_inf of the last
+ * sweep (FP64, exact from the stored values); bound_inf =
+ * gamma/(1-gamma) * residual_inf, the contraction bound on the distance to
+ * the fixed point (Alg. 3, step 3); seconds = device time between the first
+ * and the last kernel of the call (HIP events); backups = feasible
+ * (state, action) pairs per sweep x sweeps; bytes = algorithmic bytes moved
+ * (values read once and written once per sweep).                          */
+typedef struct {
+    int64_t iterations;
+    double residual_inf;
+    double bound_inf;
+    double seconds;
+    double backups;
+    double bytes;
+} mdpvi_stats;
+
+/* Validate p, derive the uniformisation constants and mixed-radix strides,
+ * and create a handle (host memory only; device scratch is allocated on
+ * first use).  Errors: MDPVI_EINVAL, MDPVI_ERANGE, MDPVI_ENOMEM.            */
+int mdp_build(const mdpvi_params *p, mdpvi_mdp_t *out);
+
+/* Free the handle and its scratch.  NULL is accepted.  The caller must have
+ * synchronised the stream of the last call.                                */
+void mdp_free(mdpvi_mdp_t h);
+
+/* N = J (C+1)^K; -1 for a NULL handle. */
+int64_t mdp_num_states(mdpvi_mdp_t h);
+/* K + 1 (placements plus the paid cloud); -1 for a NULL handle. */
+int32_t mdp_num_actions(mdpvi_mdp_t h);
+/* Feasible (state, action) pairs of one sweep; -1 for a NULL handle. */
+int64_t mdp_feasible_pairs(mdpvi_mdp_t h);
+
+/* Synchronous (Jacobi) value iteration, Alg. 3 steps 1-3 and Eq. (18).
+ * V: device float[N]; in: V^0 (e.g. zeros), out: the first iterate V^k with
+ * ||V^k - V^{k-1}||_inf < tol (strict; infinity norm exact in FP64).
+ * Sums of the Bellman backup are formed in FP64 with non-negative weights,
+ * stored values are FP32.  From a V^0 with V^0 <= T V^0 (V^0 = 0 when every
+ * reject cost is 0) the iterates increase monotonically and reach an exact
+ * FP32 fixed point, so any tol > 0 is met.
+ * Errors: MDPVI_EINVAL (NULL, tol <= 0 or NaN, max_iter < 1), MDPVI_ENOCONV
+ * (V holds V^{max_iter}), MDPVI_ENAN, MDPVI_EDEVICE, MDPVI_ENOMEM.
+ * st may be NULL.                                                           */
+int vi_solve(mdpvi_mdp_t h, float *V, double tol, int64_t max_iter,
+             void *hip_stream, mdpvi_stats *st);
+
+/* Greedy policy from a value function, Alg. 3 step 4:
+ * pi[s] = lowest-index action maximising Q(s,a) (hosts in order, the paid
+ * cloud last), Q formed in FP64 from V.
+ * V: device float[N] (policy_extract) or double[N] (policy_extract_f64);
+ * pi: device uint8[N] out; gap: device float[N] out or NULL, the best Q minus
+ * the second-best Q over feasible actions (+inf when only the paid cloud is
+ * feasible; 0 on exact ties).  Asynchronous.
+ * Errors: MDPVI_EINVAL, MDPVI_EDEVICE.                                      */
+int policy_extract(mdpvi_mdp_t h, const float *V, uint8_t *pi, float *gap,
+                   void *hip_stream);
+int policy_extract_f64(mdpvi_mdp_t h, const double *V, uint8_t *pi, float *gap,
+                       void *hip_stream);
+
+/* Fixed-policy evaluation V_pi = r_pi + gamma P_pi V_pi (the Bellman equation
+ * of Eq. (18) without the max), FP64 Jacobi sweeps.
+ * pi: device uint8[N], every entry a feasible action (checked: an infeasible
+ * placement makes the call fail with MDPVI_EINVAL before any sweep);
+ * V: device double[N], in: V^0 (warm start), out: V_pi to ||dV||_inf < tol.
+ * Errors as vi_solve.                                                       */
+int policy_eval(mdpvi_mdp_t h, const uint8_t *pi, double *V, double tol,
+                int64_t max_iter, void *hip_stream, mdpvi_stats *st);
+
+/* Fixed policies of the fast greedy heuristic (Alg. 2).
+ * kind 0 = least-loaded: the feasible host with the fewest occupied units,
+ *          lowest index on ties; the paid cloud iff no host has room.
+ * kind 1 = first-fit: the lowest-index host with room (Alg. 2 scans the VCs
+ *          in order); the paid cloud iff none has room.
+ * pi: device uint8[N] out.  Asynchronous.  Errors: MDPVI_EINVAL, MDPVI_EDEVICE. */
+int policy_greedy(mdpvi_mdp_t h, int32_t kind, uint8_t *pi, void *hip_stream);
+
+/* Thread-local text of the last failure ("" if none). */
+const char *mdpvi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDPVI_H */

@@ -1,0 +1,219 @@
+"""Python binding of libmdpvi (ctypes): value iteration for the occupancy MDP
+of vehicular bag-of-task placement on MI355X.
+
+Argument marshalling only: every step runs in the HIP kernels behind the C
+ABI of ``include/mdpvi.h``.  torch tensors supply device memory and the
+current HIP stream.  There is no CPU fallback: loading fails loudly when the
+library is missing, and every call requires tensors on a GPU.
+
+    import paper_2012_12419_amd as mdpvi
+    mdp = mdpvi.MDP(K=3, C=8, size=[1, 2], lam=[.6, .3], mu=.1, nu=.02,
+                    reward=[1, 2.5], gamma=.95)
+    V = torch.zeros(mdp.num_states, device="cuda")
+    stats = mdp.vi_solve(V, tol=1e-6)
+    pi, gap = mdp.policy_extract(V)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmdpvi.so")
+
+OK = 0
+EINVAL = -1
+ERANGE = -2
+ENOCONV = -3
+ENAN = -4
+EDEVICE = -5
+ENOMEM = -6
+_NAMES = {EINVAL: "EINVAL", ERANGE: "ERANGE", ENOCONV: "ENOCONV", ENAN: "ENAN",
+          EDEVICE: "EDEVICE", ENOMEM: "ENOMEM"}
+
+# Every function the C ABI exports, with its ctypes signature.
+_c_int64 = ctypes.c_int64
+_c_int32 = ctypes.c_int32
+_c_double = ctypes.c_double
+_vp = ctypes.c_void_p
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("K", _c_int32), ("C", _c_int32), ("J", _c_int32),
+                ("size", ctypes.POINTER(_c_int32)), ("lam", ctypes.POINTER(_c_double)),
+                ("mu", _c_double), ("nu", _c_double),
+                ("reward", ctypes.POINTER(_c_double)), ("reject_cost", ctypes.POINTER(_c_double)),
+                ("gamma", _c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", _c_int64), ("residual_inf", _c_double), ("bound_inf", _c_double),
+                ("seconds", _c_double), ("backups", _c_double), ("bytes", _c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+SIGNATURES = {
+    "mdp_build": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(_vp)]),
+    "mdp_free": (None, [_vp]),
+    "mdp_num_states": (_c_int64, [_vp]),
+    "mdp_num_actions": (_c_int32, [_vp]),
+    "mdp_feasible_pairs": (_c_int64, [_vp]),
+    "vi_solve": (ctypes.c_int, [_vp, _vp, _c_double, _c_int64, _vp, ctypes.POINTER(Stats)]),
+    "policy_extract": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "policy_extract_f64": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "policy_eval": (ctypes.c_int, [_vp, _vp, _vp, _c_double, _c_int64, _vp, ctypes.POINTER(Stats)]),
+    "policy_greedy": (ctypes.c_int, [_vp, _c_int32, _vp, _vp]),
+    "mdpvi_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmdpvi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2012_12419_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class MdpviError(RuntimeError):
+    def __init__(self, code: int, msg: str, stats: Optional[dict] = None):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+        self.stats = stats
+
+
+def _check(code: int, stats: Optional[Stats] = None):
+    if code != OK:
+        msg = load().mdpvi_last_error().decode()
+        raise MdpviError(code, msg, stats.as_dict() if stats is not None else None)
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_tensor(t, dtype, n: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (there is no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} entries, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(K: int, C: int, size: Sequence[int], lam: Sequence[float], mu: float, nu: float,
+                reward: Sequence[float], gamma: float,
+                reject_cost: Optional[Sequence[float]] = None):
+    """ctypes Params plus the arrays it points into (keep both alive)."""
+    J = len(size)
+    keep = [(_c_int32 * J)(*[int(s) for s in size]), (_c_double * J)(*[float(x) for x in lam]),
+            (_c_double * J)(*[float(x) for x in reward])]
+    rc = (_c_double * J)(*[float(x) for x in reject_cost]) if reject_cost is not None else None
+    keep.append(rc)
+    p = Params(int(K), int(C), J, keep[0], keep[1], float(mu), float(nu), keep[2],
+               ctypes.cast(rc, ctypes.POINTER(_c_double)) if rc is not None else None, float(gamma))
+    return p, keep
+
+
+class MDP:
+    """Handle of one MDP instance in libmdpvi."""
+
+    def __init__(self, K: int, C: int, size: Sequence[int], lam: Sequence[float], mu: float,
+                 nu: float, reward: Sequence[float], gamma: float,
+                 reject_cost: Optional[Sequence[float]] = None):
+        lib = load()
+        p, keep = make_params(K, C, size, lam, mu, nu, reward, gamma, reject_cost)
+        h = ctypes.c_void_p()
+        _check(lib.mdp_build(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self.K, self.C, self.J = int(K), int(C), len(size)
+        self.gamma = float(gamma)
+        self.num_states = int(lib.mdp_num_states(h))
+        self.num_actions = int(lib.mdp_num_actions(h))
+        self.feasible_pairs = int(lib.mdp_feasible_pairs(h))
+        self.n_occ = self.num_states // self.J
+
+    @classmethod
+    def from_instance(cls, inst) -> "MDP":
+        return cls(inst.K, inst.C, inst.size, inst.lam, inst.mu, inst.nu, inst.reward,
+                   inst.gamma, inst.reject_cost)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().mdp_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --------------------------------------------------------------- calls
+    def vi_solve(self, V, tol: float = 1e-6, max_iter: int = 1_000_000, stream=None) -> dict:
+        import torch
+        st = Stats()
+        v = _dev_tensor(V, torch.float32, self.num_states, "V")
+        _check(load().vi_solve(self._h, v, float(tol), int(max_iter), _stream_ptr(stream),
+                               ctypes.byref(st)), st)
+        return st.as_dict()
+
+    def policy_extract(self, V, pi=None, gap=None, want_gap: bool = True, stream=None):
+        import torch
+        n = self.num_states
+        if pi is None:
+            pi = torch.empty(n, dtype=torch.uint8, device=V.device)
+        if gap is None and want_gap:
+            gap = torch.empty(n, dtype=torch.float32, device=V.device)
+        p = _dev_tensor(pi, torch.uint8, n, "pi")
+        g = _dev_tensor(gap, torch.float32, n, "gap") if gap is not None else None
+        if V.dtype == torch.float64:
+            v = _dev_tensor(V, torch.float64, n, "V")
+            _check(load().policy_extract_f64(self._h, v, p, g, _stream_ptr(stream)))
+        else:
+            v = _dev_tensor(V, torch.float32, n, "V")
+            _check(load().policy_extract(self._h, v, p, g, _stream_ptr(stream)))
+        return pi, gap
+
+    def policy_eval(self, pi, V=None, tol: float = 1e-12, max_iter: int = 10_000_000,
+                    stream=None):
+        import torch
+        n = self.num_states
+        if V is None:
+            V = torch.zeros(n, dtype=torch.float64, device=pi.device)
+        st = Stats()
+        _check(load().policy_eval(self._h, _dev_tensor(pi, torch.uint8, n, "pi"),
+                                  _dev_tensor(V, torch.float64, n, "V"), float(tol),
+                                  int(max_iter), _stream_ptr(stream), ctypes.byref(st)), st)
+        return V, st.as_dict()
+
+    def policy_greedy(self, kind: str = "least_loaded", pi=None, stream=None):
+        import torch
+        code = {"least_loaded": 0, "first_fit": 1}[kind]
+        if pi is None:
+            pi = torch.empty(self.num_states, dtype=torch.uint8, device="cuda")
+        _check(load().policy_greedy(self._h, code, _dev_tensor(pi, torch.uint8, self.num_states, "pi"),
+                                    _stream_ptr(stream)))
+        return pi

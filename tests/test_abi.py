@@ -1,0 +1,104 @@
+"""The C-ABI library loads, exports every symbol the header declares, and
+validates parameters on the host (no GPU needed for any of this)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2012_12419_amd as mdpvi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[\w ]+?\**\s*\b(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = mdpvi.load()
+    declared = _declared()
+    assert "vi_solve" in declared and "mdp_build" in declared
+    for name in declared:
+        assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+    assert set(declared) <= set(mdpvi.SIGNATURES), set(declared) - set(mdpvi.SIGNATURES)
+
+
+def _build(**kw):
+    base = dict(K=3, C=8, size=[1, 2], lam=[0.6, 0.3], mu=0.1, nu=0.02, reward=[1.0, 2.5],
+                gamma=0.95, reject_cost=None)
+    base.update(kw)
+    p, keep = mdpvi.make_params(**base)
+    h = ctypes.c_void_p()
+    rc = mdpvi.load().mdp_build(ctypes.byref(p), ctypes.byref(h))
+    return rc, h
+
+
+def test_build_and_counts():
+    rc, h = _build()
+    lib = mdpvi.load()
+    assert rc == mdpvi.OK
+    assert lib.mdp_num_states(h) == 1458
+    assert lib.mdp_num_actions(h) == 4
+    assert lib.mdp_feasible_pairs(h) == 5103
+    lib.mdp_free(h)
+    lib.mdp_free(None)
+    assert lib.mdp_num_states(None) == -1
+
+
+@pytest.mark.parametrize("kw,code,text", [
+    (dict(gamma=1.0), mdpvi.EINVAL, "gamma"),
+    (dict(gamma=-0.1), mdpvi.EINVAL, "gamma"),
+    (dict(gamma=float("nan")), mdpvi.EINVAL, "gamma"),
+    (dict(size=[1, 9]), mdpvi.EINVAL, "size[1]"),
+    (dict(size=[0, 2]), mdpvi.EINVAL, "size[0]"),
+    (dict(lam=[-0.1, 0.3]), mdpvi.EINVAL, "lambda[0]"),
+    (dict(lam=[0.0, 0.0]), mdpvi.EINVAL, "sum of lambda"),
+    (dict(lam=[float("inf"), 0.3]), mdpvi.EINVAL, "lambda[0]"),
+    (dict(mu=-1.0), mdpvi.EINVAL, "mu"),
+    (dict(nu=float("nan")), mdpvi.EINVAL, "nu"),
+    (dict(reward=[1.0, float("nan")]), mdpvi.EINVAL, "reward[1]"),
+    (dict(reject_cost=[0.0, float("inf")]), mdpvi.EINVAL, "reject_cost[1]"),
+    (dict(K=0), mdpvi.EINVAL, "K=0"),
+    (dict(K=17), mdpvi.EINVAL, "K=17"),
+    (dict(C=0, size=[1, 1]), mdpvi.EINVAL, "C=0"),
+    (dict(size=[1] * 9, lam=[0.1] * 9, reward=[1.0] * 9), mdpvi.EINVAL, "J=9"),
+    (dict(K=16, C=20, size=[1], lam=[1.0], reward=[1.0]), mdpvi.ERANGE, "2^"),
+    (dict(K=11, C=8, size=[1], lam=[1.0], reward=[1.0]), mdpvi.ERANGE, "occupancies"),
+])
+def test_validation(kw, code, text):
+    rc, h = _build(**kw)
+    assert rc == code
+    assert h.value is None
+    assert text in mdpvi.load().mdpvi_last_error().decode()
+
+
+def test_null_arguments():
+    lib = mdpvi.load()
+    h = ctypes.c_void_p()
+    assert lib.mdp_build(None, ctypes.byref(h)) == mdpvi.EINVAL
+    assert lib.vi_solve(None, None, 1e-6, 10, None, None) == mdpvi.EINVAL
+    assert lib.policy_extract(None, None, None, None, None) == mdpvi.EINVAL
+    assert lib.policy_eval(None, None, None, 1e-6, 10, None, None) == mdpvi.EINVAL
+    assert lib.policy_greedy(None, 0, None, None) == mdpvi.EINVAL
+    rc, h = _build()
+    assert lib.vi_solve(h, None, 1e-6, 10, None, None) == mdpvi.EINVAL
+    fake = ctypes.c_void_p(16)
+    assert lib.vi_solve(h, fake, 0.0, 10, None, None) == mdpvi.EINVAL
+    assert lib.vi_solve(h, fake, float("nan"), 10, None, None) == mdpvi.EINVAL
+    assert lib.vi_solve(h, fake, 1e-6, 0, None, None) == mdpvi.EINVAL
+    assert lib.policy_greedy(h, 2, fake, None) == mdpvi.EINVAL
+    lib.mdp_free(h)
+
+
+def test_python_binding_refuses_cpu_tensors():
+    import torch
+    m = mdpvi.MDP(3, 8, [1, 2], [0.6, 0.3], 0.1, 0.02, [1.0, 2.5], 0.95)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        m.vi_solve(torch.zeros(m.num_states))

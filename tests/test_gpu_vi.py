@@ -1,0 +1,223 @@
+"""GPU parity of value iteration, extraction, evaluation and the greedy
+heuristic against the FP64 oracle (through the C ABI via the binding).
+
+Small instances (seconds for the oracle, several 256-thread tiles and a
+ragged tail) are compared element by element with the oracle's fixed point.
+Full-size instances are checked through properties that hold at any size:
+the GPU iterate is a fixed point of the oracle's Bellman operator up to one
+FP32 rounding at every state (one vectorised oracle sweep), which by the
+contraction bound certifies ||V_gpu - V*||_inf, and the GPU policy is the
+oracle's argmax at sampled states computed one by one.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import model, vi
+from tests.gpu_util import EVAL_REL, gap_mask, torch_cuda, vi_close
+
+pytestmark = pytest.mark.gpu
+
+
+def lower_bound(inst):
+    lam = np.asarray(inst.lam)
+    Lam = lam.sum() + inst.K * inst.C * inst.mu + inst.K * inst.nu
+    return -lam.sum() / Lam * max(inst.reject_cost) / (1 - inst.gamma)
+
+
+def _cases():
+    out = [("small_parity", W.small_parity()),
+           ("dense_copy_K2C6", W.gradient_instance(2, 6)),
+           ("tiny_K1C1J1", W.make(1, 1, (1,), (0.5,), 0.3, 0.1, (1.0,), 0.9)),
+           ("sub_wave_K2C4J1", W.make(2, 4, (1,), (0.7,), 0.1, 0.02, (1.2,), 0.93)),
+           ("J8_K1C8", W.make(1, 8, tuple(range(1, 9)), [0.1 * (j + 1) for j in range(8)], 0.1,
+                             0.02, [0.8 * (j + 1) for j in range(8)], 0.9)),
+           ("K16_C1", W.make(16, 1, (1,), (1.5,), 0.1, 0.01, (1.0,), 0.9)),
+           ("size_eq_C", W.make(3, 3, (1, 3), (0.5, 0.4), 0.15, 0.03, (1.0, 4.0), 0.95)),
+           ("ragged_K4C12J3", W.make(4, 12, (1, 2, 3), (0.6, 0.5, 0.3), 0.08, 0.02, (1.0, 2.1, 3.3),
+                                     0.97)),
+           ("mu0_nu0", W.make(2, 5, (1, 2), (0.6, 0.3), 0.0, 0.0, (1.0, 2.5), 0.9))]
+    for seed in range(6):
+        out.append((f"random{seed}", W.random_small(seed, K_max=4, C_max=6)))
+    for seed in range(3):
+        base = W.random_small(100 + seed, K_max=3, C_max=5)
+        out.append((f"reject{seed}", W.random_rewards_with_reject(seed, base)))
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module")
+def mdpvi():
+    torch_cuda()
+    import paper_2012_12419_amd as m
+    m.load()
+    return m
+
+
+@pytest.mark.parametrize("name,inst", CASES, ids=[c[0] for c in CASES])
+def test_vi_extract_eval_parity(mdpvi, name, inst):
+    import torch
+    print(f"case {name}: K={inst.K} C={inst.C} J={inst.J} N={inst.num_states}", flush=True)
+    g = vi.grid(inst)
+    star = vi.value_iteration(inst, 1e-13, g=g).V
+    pi_o, gap_o = vi.extract(inst, star, g)
+    Q1 = vi.q_table(inst, star, g).max(axis=1)
+
+    mdp = mdpvi.MDP.from_instance(inst)
+    assert mdp.num_states == inst.num_states
+    assert mdp.feasible_pairs == vi.feasible_pairs(inst)
+    V = torch.full((mdp.num_states,), lower_bound(inst), dtype=torch.float32, device="cuda")
+    st = mdp.vi_solve(V, tol=1e-7, max_iter=200_000)
+    Vg = V.cpu().numpy()
+    vi_close(Vg, star)
+    assert st["residual_inf"] < 1e-7
+
+    # extraction from the FP32 values: the chosen action is optimal to the
+    # accuracy of those values
+    pi_g, gap_g = mdp.policy_extract(V)
+    pi_g = pi_g.cpu().numpy()
+    Qs = vi.q_table(inst, star, g)
+    chosen = Qs[np.arange(pi_g.size), pi_g.astype(np.int64)]
+    assert np.all(np.isfinite(chosen)), "GPU chose an infeasible action"
+    assert np.max(Q1 - chosen) <= 2e-5 * np.max(np.abs(star))
+
+    # FP64 evaluation of that policy, then one improvement step in FP64
+    Vp, st2 = mdp.policy_eval(torch.from_numpy(pi_g).cuda(), V.double(), tol=1e-12)
+    ref = vi.policy_eval(inst, pi_g, tol=1e-13, g=g)
+    assert np.max(np.abs(Vp.cpu().numpy() - ref)) <= EVAL_REL * np.max(np.abs(ref))
+    pi2, gap2 = mdp.policy_extract(Vp)
+    pi2 = pi2.cpu().numpy()
+    mask = gap_mask(Q1, gap_o, star)
+    assert np.array_equal(pi2[mask], pi_o[mask]), f"{np.sum(pi2[mask] != pi_o[mask])} policy mismatches"
+    gap2 = gap2.cpu().numpy()
+    fin = np.isfinite(gap_o)
+    assert np.array_equal(np.isfinite(gap2), fin)
+    assert np.allclose(gap2[fin], gap_o[fin], rtol=1e-5, atol=1e-6 * np.max(np.abs(star)))
+    mdp.close()
+
+
+@pytest.mark.parametrize("name,inst", CASES[:8], ids=[c[0] for c in CASES[:8]])
+def test_greedy_bit_exact(mdpvi, name, inst):
+    import torch
+    mdp = mdpvi.MDP.from_instance(inst)
+    for kind in ["least_loaded", "first_fit"]:
+        pi = mdp.policy_greedy(kind).cpu().numpy()
+        assert np.array_equal(pi, vi.greedy_policy(inst, kind))
+        V, _ = mdp.policy_eval(torch.from_numpy(pi).cuda(), tol=1e-12)
+        ref = vi.policy_eval(inst, pi, tol=1e-13)
+        assert np.max(np.abs(V.cpu().numpy() - ref)) <= EVAL_REL * np.max(np.abs(ref))
+
+
+def test_deterministic(mdpvi):
+    import torch
+    inst = W.make(4, 9, (1, 2), (0.6, 0.4), 0.1, 0.02, (1.0, 2.4), 0.98)
+    mdp = mdpvi.MDP.from_instance(inst)
+    outs = []
+    for _ in range(2):
+        V = torch.zeros(mdp.num_states, device="cuda")
+        st = mdp.vi_solve(V, tol=1e-7)
+        pi, gap = mdp.policy_extract(V)
+        outs.append((V.cpu().numpy().copy(), pi.cpu().numpy().copy(), st["iterations"]))
+    assert outs[0][2] == outs[1][2]
+    assert np.array_equal(outs[0][0].view(np.uint32), outs[1][0].view(np.uint32))
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_max_iter_gives_enoconv_and_valid_iterate(mdpvi):
+    import torch
+    inst = W.small_parity()
+    mdp = mdpvi.MDP.from_instance(inst)
+    for k in [1, 2, 3, 7]:
+        V = torch.zeros(mdp.num_states, device="cuda")
+        with pytest.raises(mdpvi.MdpviError) as ei:
+            mdp.vi_solve(V, tol=1e-9, max_iter=k)
+        assert ei.value.code == mdpvi.ENOCONV
+        assert ei.value.stats["iterations"] == k
+        ref = vi.value_iteration(inst, 0.0, max_iter=k).V
+        assert np.max(np.abs(V.cpu().numpy() - ref)) <= 1e-6 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_nan_is_reported(mdpvi):
+    import torch
+    inst = W.small_parity()
+    mdp = mdpvi.MDP.from_instance(inst)
+    V = torch.zeros(mdp.num_states, device="cuda")
+    V[17] = float("nan")
+    with pytest.raises(mdpvi.MdpviError) as ei:
+        mdp.vi_solve(V, tol=1e-6, max_iter=50)
+    assert ei.value.code == mdpvi.ENAN
+
+
+def test_infeasible_policy_rejected(mdpvi):
+    import torch
+    inst = W.small_parity()
+    mdp = mdpvi.MDP.from_instance(inst)
+    pi = torch.zeros(mdp.num_states, dtype=torch.uint8, device="cuda")   # host 0 even when full
+    with pytest.raises(mdpvi.MdpviError) as ei:
+        mdp.policy_eval(pi, tol=1e-9)
+    assert ei.value.code == mdpvi.EINVAL
+    pi.fill_(9)
+    with pytest.raises(mdpvi.MdpviError) as ei:
+        mdp.policy_eval(pi, tol=1e-9)
+    assert ei.value.code == mdpvi.EINVAL
+
+
+def test_warm_start_and_loose_tol(mdpvi):
+    import torch
+    inst = W.small_parity()
+    star = vi.value_iteration(inst, 1e-13).V
+    mdp = mdpvi.MDP.from_instance(inst)
+    V = torch.from_numpy(star.astype(np.float32)).cuda()
+    st = mdp.vi_solve(V, tol=1e-5)
+    assert st["iterations"] <= 5
+    vi_close(V.cpu().numpy(), star)
+    # a loose tolerance stops early; the contraction bound holds
+    V = torch.zeros(mdp.num_states, device="cuda")
+    st = mdp.vi_solve(V, tol=1e-2)
+    err = np.max(np.abs(V.cpu().numpy() - star))
+    assert err <= st["bound_inf"] + 1e-5
+    ref = vi.value_iteration(inst, 1e-2)
+    assert st["iterations"] == ref.iterations
+
+
+def _full_size_check(mdpvi, inst, n_sample=300, seed=0):
+    import torch
+    mdp = mdpvi.MDP.from_instance(inst)
+    V = torch.zeros(mdp.num_states, device="cuda")
+    st = mdp.vi_solve(V, tol=1e-6)
+    print(f"N={mdp.num_states} sweeps={st['iterations']} seconds={st['seconds']:.4f}", flush=True)
+    Vg = V.cpu().numpy().astype(np.float64)
+    # one oracle sweep from the GPU's values: fixed point up to one FP32 rounding
+    g = vi.grid(inst)
+    Q = vi.q_table(inst, Vg, g)
+    TV = Q.max(axis=1)
+    half_ulp = np.spacing(np.abs(Vg).astype(np.float32)).astype(np.float64) / 2
+    assert np.all(np.abs(TV - Vg) <= 1.0001 * half_ulp + 1e-6), np.max(np.abs(TV - Vg) - half_ulp)
+    bound = np.max(np.abs(TV - Vg)) / (1 - inst.gamma)
+    assert bound <= 1e-5 * np.max(np.abs(Vg))
+    # policy at sampled states, each computed one by one by the oracle
+    pi, gap = mdp.policy_extract(V)
+    pi = pi.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    for s in rng.integers(0, mdp.num_states, n_sample):
+        best, arg, qs = model.bellman_backup(inst, Vg, int(s))
+        srt = sorted(qs)
+        clear = len(qs) == 1 or (srt[-1] - srt[-2]) > 1e-12 * abs(best)
+        if clear:
+            assert pi[s] == arg, (s, pi[s], arg, qs)
+    # the whole policy agrees with the vectorised oracle argmax at the GPU values
+    pi_o = np.argmax(Q, axis=1)
+    Qs = np.sort(Q, axis=1)
+    clear = ~np.isfinite(Qs[:, -2]) | ((Qs[:, -1] - Qs[:, -2]) > 1e-12 * np.abs(Qs[:, -1]))
+    assert np.array_equal(pi[clear], pi_o[clear])
+    return mdp, V, pi, st
+
+
+def test_gradient_config_size(mdpvi):
+    _full_size_check(mdpvi, W.gradient_instance())
+
+
+def test_large_single_instance(mdpvi):
+    _full_size_check(mdpvi, W.large_single())
