@@ -1,0 +1,217 @@
+#!/usr/bin/env python
+"""Throughput of the value-iteration hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+One step is one pass of the whole hot path over the large single instance
+(K=6 hosts, C=10 units, J=3 classes of sizes 1,2,3: 5,314,683 states,
+gamma 0.99, seeded rates), with every input already resident in HBM:
+
+  1. V := 0; vi_solve to ||dV||_inf < 1e-6 (Jacobi sweeps, FP32 values,
+     FP64 sums);
+  2. policy_extract (greedy policy pi* and Q gap);
+  3. policy_eval of pi* in FP64 (warm start from V) and one FP64
+     improvement step (policy_extract_f64) that certifies pi*;
+  4. policy_greedy (least-loaded heuristic) and its FP64 policy_eval.
+
+value = state-action backups per second over the timed steps: feasible
+(state, action) pairs per value-iteration sweep times its sweeps, plus one
+backup per state per fixed-policy sweep, divided by the wall time of the
+steps.  The JSON line also carries the time to ||dV||_inf < 1e-6, the
+roofline of the dominant kernel (algorithmic bytes per launch over the
+average launch duration, both kernels' durations measured with HIP events
+bracketing every sweep on its stream) and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "state-action backups/s + time to ‖ΔV‖∞<1e-6; batched vs per-instance, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+VI_BYTES_PER_STATE = 8.0      # FP32 value read once + written once per sweep
+EVAL_BYTES_PER_STATE = 17.0   # FP64 value read + write, uint8 policy read
+
+
+def workload(name: str):
+    import workloads as W
+    if name == "large_single":
+        return W.large_single(), "K=6 C=10 J=3 sizes(1,2,3) seed 2, gamma 0.99: 5,314,683 states"
+    if name == "large_single_k7":
+        return (W.large_single(K=7),
+                "K=7 C=10 J=3 sizes(1,2,3) seed 2, gamma 0.99: 58,461,513 states (exceeds the 256 MB last-level cache)")
+    if name == "gradient":
+        return W.gradient_instance(), "K=5 C=10 J=2 sizes(1,2), gamma 0.98: 322,102 states"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(inst, sweeps: int) -> dict:
+    """The FP64 NumPy oracle's Jacobi sweep, single-threaded, on `sweeps`
+    sweeps from V = 0 of the same instance."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import vi
+    with threadpool_limits(limits=1):
+        g = vi.grid(inst)
+        pairs = vi.feasible_pairs(inst)
+        V = np.zeros(inst.num_states)
+        t0 = time.perf_counter()
+        for _ in range(sweeps):
+            V = vi.bellman(inst, V, g)
+        dt = time.perf_counter() - t0
+    return {"value": pairs * sweeps / dt, "unit": "backups/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sweeps} FP64 Jacobi sweeps from V=0 of the same instance "
+                      f"({pairs} feasible pairs each, {dt:.1f} s), NumPy on one host thread"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large_single")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--eval-tol", type=float, default=1e-10)
+    ap.add_argument("--cpu-sweeps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="do not bracket sweeps with events (roofline fields become null)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(instances are independent; see the sharding design). Run with --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2012_12419_amd as mdpvi
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    inst, desc = workload(args.workload)
+    mdp = mdpvi.MDP.from_instance(inst)
+    mdp.set_timing(not args.no_timing)
+    N = mdp.num_states
+    dev = "cuda:0"
+    V = torch.zeros(N, dtype=torch.float32, device=dev)
+    Vp = torch.zeros(N, dtype=torch.float64, device=dev)
+    Vg = torch.zeros(N, dtype=torch.float64, device=dev)
+    pi = torch.empty(N, dtype=torch.uint8, device=dev)
+    pi2 = torch.empty(N, dtype=torch.uint8, device=dev)
+    pig = torch.empty(N, dtype=torch.uint8, device=dev)
+    gap = torch.empty(N, dtype=torch.float32, device=dev)
+    lam = torch.tensor(inst.lam, dtype=torch.float64)
+    c = lam / lam.sum()
+    empty = torch.arange(inst.J, device=dev) * mdp.n_occ
+
+    def step():
+        V.zero_()
+        s_vi = mdp.vi_solve(V, tol=args.tol)
+        mdp.policy_extract(V, pi=pi, gap=gap)
+        Vp.copy_(V)
+        _, s_ev = mdp.policy_eval(pi, Vp, tol=args.eval_tol)
+        mdp.policy_extract(Vp, pi=pi2, gap=None, want_gap=False)
+        mdp.policy_greedy("least_loaded", pi=pig)
+        Vg.zero_()
+        _, s_g = mdp.policy_eval(pig, Vg, tol=args.eval_tol)
+        return s_vi, s_ev, s_g
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        recs.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    backups = sum(r[0]["backups"] + N * (r[1]["iterations"] + r[2]["iterations"]) for r in recs)
+    vi_sweeps = [r[0]["iterations"] for r in recs]
+    ev_sweeps = [r[1]["iterations"] for r in recs]
+    g_sweeps = [r[2]["iterations"] for r in recs]
+    t_tol = sum(r[0]["seconds"] for r in recs) / len(recs)
+
+    roof = None
+    kernels = {}
+    if not args.no_timing:
+        vi_k = sum(r[0]["sweep_seconds"] for r in recs)
+        ev_k = sum(r[1]["sweep_seconds"] + r[2]["sweep_seconds"] for r in recs)
+        n_vi = sum(vi_sweeps)
+        n_ev = sum(ev_sweeps) + sum(g_sweeps)
+        for name, tot, cnt, bps in [("vi_sweep_kernel", vi_k, n_vi, VI_BYTES_PER_STATE),
+                                    ("eval_sweep_kernel", ev_k, n_ev, EVAL_BYTES_PER_STATE)]:
+            avg = tot / cnt
+            ach = bps * N / avg / 1e9
+            kernels[name] = {"launches": cnt, "avg_us": avg * 1e6, "bytes_per_launch": bps * N,
+                             "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
+                             "share_of_step": tot / elapsed}
+        dom = max(kernels, key=lambda k: kernels[k]["share_of_step"])
+        kd = kernels[dom]
+        roof = {"bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": kd["frac"], "traffic": None, "kernel": dom}
+
+    Vh = V.double()
+    J_opt = float((c.to(dev) * Vp[empty]).sum())
+    J_greedy = float((c.to(dev) * Vg[empty]).sum())
+    changed = int((pi2 != pi).sum())
+
+    out = {
+        "metric": METRIC,
+        "value": backups / elapsed,
+        "unit": "backups/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "states": N,
+                   "feasible_pairs_per_sweep": mdp.feasible_pairs, "tol": args.tol,
+                   "eval_tol": args.eval_tol, "values": "FP32 storage, FP64 sums (VI); FP64 (evaluation)"},
+        "time_to_tol_s": t_tol,
+        "vi_sweeps": vi_sweeps,
+        "eval_sweeps": ev_sweeps,
+        "greedy_eval_sweeps": g_sweeps,
+        "vi_backups_per_s": sum(r[0]["backups"] for r in recs) / sum(r[0]["seconds"] for r in recs),
+        "J_optimal": J_opt,
+        "J_greedy_least_loaded": J_greedy,
+        "improvement_step_changed_states": changed,
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    del Vh
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

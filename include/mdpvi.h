@@ -86,7 +86,9 @@ typedef struct mdpvi_mdp *mdpvi_mdp_t;
  * the fixed point (Alg. 3, step 3); seconds = device time between the first
  * and the last kernel of the call (HIP events); backups = feasible
  * (state, action) pairs per sweep x sweeps; bytes = algorithmic bytes moved
- * (values read once and written once per sweep).                          */
+ * (values read once and written once per sweep); sweep_seconds = sum of the
+ * durations of the sweep kernels that did work, each bracketed by its own
+ * pair of HIP events on the call's stream (0 unless mdp_set_timing(h, 1)).  */
 typedef struct {
     int64_t iterations;
     double residual_inf;
@@ -94,6 +96,7 @@ typedef struct {
     double seconds;
     double backups;
     double bytes;
+    double sweep_seconds;
 } mdpvi_stats;
 
 /* Validate p, derive the uniformisation constants and mixed-radix strides,
@@ -154,6 +157,70 @@ int policy_eval(mdpvi_mdp_t h, const uint8_t *pi, double *V, double tol,
  *          in order); the paid cloud iff none has room.
  * pi: device uint8[N] out.  Asynchronous.  Errors: MDPVI_EINVAL, MDPVI_EDEVICE. */
 int policy_greedy(mdpvi_mdp_t h, int32_t kind, uint8_t *pi, void *hip_stream);
+
+/* Gradient of the expected discounted reward from the empty system,
+ *   J = sum_e c_e V_pi(0, e),   c_e = lambda[e] / sum_j lambda[j],
+ * with respect to theta = (lambda[0..J-1], mu, nu, reward[0..J-1]), the policy
+ * held fixed (for the optimal pi of Eq. (18) this is the derivative of the
+ * optimal J wherever the optimal action is unique up to ties between
+ * equivalent hosts).  Adjoint method: w solves (I - gamma P_pi)^T w = c by
+ * transposed Jacobi sweeps w <- c + gamma P_pi^T w (FP32 w, FP64 sums, stop at
+ * ||dw||_1 < tol), then one pass forms
+ *   dJ/dtheta = sum_s w(s) (d r_pi(s) + gamma d(P_pi V_pi)(s)) + sum_e d c_e V_pi(0, e)
+ * in FP64 with a fixed-order reduction (bitwise reproducible).
+ * pi: device uint8[N] (feasible, checked); V_pi: device double[N], the value
+ * of pi (policy_eval); w: device float[N], in: w^0 (e.g. zeros), out: the
+ * adjoint weights; grad: host double[2J+2] out, ordered lambda[0..J-1], mu,
+ * nu, reward[0..J-1]; objective: host double out (J) or NULL.
+ * Errors: as policy_eval; on MDPVI_ENOCONV grad is formed from the last w.  */
+int vi_adjoint(mdpvi_mdp_t h, const uint8_t *pi, const double *V_pi, float *w,
+               double *grad, double *objective, double tol, int64_t max_iter,
+               void *hip_stream, mdpvi_stats *st);
+
+/* J = sum_e c_e V(0, e) of a device double[N] value array (host double out).
+ * Synchronous.  Errors: MDPVI_EINVAL, MDPVI_EDEVICE, MDPVI_ENOMEM.          */
+int policy_objective(mdpvi_mdp_t h, const double *V, double *out, void *hip_stream);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent instances (a parameter sweep over rates and fleet sizes)
+ * solved together.  Per-state arrays of a batch are the instances' arrays
+ * concatenated in instance order; batch_offsets gives the n+1 offsets.
+ * Each instance keeps its own stopping test.  Instances whose two FP32 value
+ * copies fit one workgroup's LDS (about 20k states) are solved LDS-resident,
+ * one workgroup each, in one persistent launch; larger ones advance one sweep
+ * per round kernel over all of them at once, concurrently on a second stream
+ * owned by the batch.  Every instance must have fewer than 2^31 states.   */
+typedef struct mdpvi_batch *mdpvi_batch_t;
+
+/* p: host array of n parameter blocks (validated as mdp_build).  Host only.
+ * Errors: MDPVI_EINVAL (the message names the instance), MDPVI_ERANGE,
+ * MDPVI_ENOMEM.                                                             */
+int mdp_build_batch(const mdpvi_params *p, int32_t n, mdpvi_batch_t *out);
+void mdp_free_batch(mdpvi_batch_t b);
+/* n; -1 for NULL. */
+int32_t batch_num_instances(mdpvi_batch_t b);
+/* States of instance i, or of the whole batch for i = -1; -1 if invalid. */
+int64_t batch_num_states(mdpvi_batch_t b, int32_t i);
+/* Feasible (state, action) pairs per sweep of instance i (-1: sum). */
+int64_t batch_feasible_pairs(mdpvi_batch_t b, int32_t i);
+/* offsets: host int64[n+1] out, offsets[i] = first state of instance i. */
+int batch_offsets(mdpvi_batch_t b, int64_t *offsets);
+
+/* vi_solve for every instance (same tol and max_iter).  V: device
+ * float[total states], in V^0, out each instance's final iterate.
+ * iterations, residuals: host arrays of n (or NULL) with each instance's
+ * sweeps and final residual.  st: aggregate (max iterations, total backups
+ * and bytes, device seconds of the whole call).  Errors: as vi_solve;
+ * MDPVI_ENOCONV / MDPVI_ENAN if any instance is affected (all outputs valid). */
+int vi_solve_batch(mdpvi_batch_t b, float *V, double tol, int64_t max_iter,
+                   void *hip_stream, mdpvi_stats *st, int64_t *iterations,
+                   double *residuals);
+
+/* Per-sweep kernel timing for the iterative calls of this handle: when on,
+ * every sweep launch is bracketed by two HIP events and their elapsed times
+ * are summed into mdpvi_stats.sweep_seconds (a measurement aid; it adds two
+ * event records per sweep).  Errors: MDPVI_EINVAL (NULL handle).           */
+int mdp_set_timing(mdpvi_mdp_t h, int32_t per_sweep_events);
 
 /* Thread-local text of the last failure ("" if none). */
 const char *mdpvi_last_error(void);

@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", _c_int64), ("residual_inf", _c_double), ("bound_inf", _c_double),
-                ("seconds", _c_double), ("backups", _c_double), ("bytes", _c_double)]
+                ("seconds", _c_double), ("backups", _c_double), ("bytes", _c_double),
+                ("sweep_seconds", _c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -67,6 +68,19 @@ SIGNATURES = {
     "policy_extract_f64": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "policy_eval": (ctypes.c_int, [_vp, _vp, _vp, _c_double, _c_int64, _vp, ctypes.POINTER(Stats)]),
     "policy_greedy": (ctypes.c_int, [_vp, _c_int32, _vp, _vp]),
+    "vi_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_c_double),
+                                  ctypes.POINTER(_c_double), _c_double, _c_int64, _vp,
+                                  ctypes.POINTER(Stats)]),
+    "policy_objective": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_c_double), _vp]),
+    "mdp_build_batch": (ctypes.c_int, [ctypes.POINTER(Params), _c_int32, ctypes.POINTER(_vp)]),
+    "mdp_free_batch": (None, [_vp]),
+    "batch_num_instances": (_c_int32, [_vp]),
+    "batch_num_states": (_c_int64, [_vp, _c_int32]),
+    "batch_feasible_pairs": (_c_int64, [_vp, _c_int32]),
+    "batch_offsets": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int64)]),
+    "vi_solve_batch": (ctypes.c_int, [_vp, _vp, _c_double, _c_int64, _vp, ctypes.POINTER(Stats),
+                                      ctypes.POINTER(_c_int64), ctypes.POINTER(_c_double)]),
+    "mdp_set_timing": (ctypes.c_int, [_vp, _c_int32]),
     "mdpvi_last_error": (ctypes.c_char_p, []),
 }
 
@@ -171,6 +185,10 @@ class MDP:
         except Exception:
             pass
 
+    def set_timing(self, on: bool = True):
+        """Bracket every sweep with HIP events (stats['sweep_seconds'])."""
+        _check(load().mdp_set_timing(self._h, 1 if on else 0))
+
     # --------------------------------------------------------------- calls
     def vi_solve(self, V, tol: float = 1e-6, max_iter: int = 1_000_000, stream=None) -> dict:
         import torch
@@ -217,3 +235,73 @@ class MDP:
         _check(load().policy_greedy(self._h, code, _dev_tensor(pi, torch.uint8, self.num_states, "pi"),
                                     _stream_ptr(stream)))
         return pi
+
+    def vi_adjoint(self, pi, V_pi, w=None, tol: float = 1e-10, max_iter: int = 10_000_000,
+                   stream=None):
+        """dJ/dtheta for theta = (lambda_1..J, mu, nu, r_1..J) at the fixed policy pi
+        with value V_pi; returns (grad list, J, w, stats)."""
+        import torch
+        n = self.num_states
+        if w is None:
+            w = torch.zeros(n, dtype=torch.float32, device=pi.device)
+        g = (_c_double * (2 * self.J + 2))()
+        Jv = _c_double()
+        st = Stats()
+        _check(load().vi_adjoint(self._h, _dev_tensor(pi, torch.uint8, n, "pi"),
+                                 _dev_tensor(V_pi, torch.float64, n, "V_pi"),
+                                 _dev_tensor(w, torch.float32, n, "w"), g, ctypes.byref(Jv),
+                                 float(tol), int(max_iter), _stream_ptr(stream), ctypes.byref(st)), st)
+        return list(g), Jv.value, w, st.as_dict()
+
+    def objective(self, V, stream=None) -> float:
+        """J = sum_e lambda_e / sum_j lambda_j V(0, e) of a device FP64 value array."""
+        import torch
+        out = _c_double()
+        _check(load().policy_objective(self._h, _dev_tensor(V, torch.float64, self.num_states, "V"),
+                                       ctypes.byref(out), _stream_ptr(stream)))
+        return out.value
+
+
+class Batch:
+    """Handle of a batch of independent instances (concatenated per-state arrays)."""
+
+    def __init__(self, instances):
+        lib = load()
+        self._keep = []
+        arr = (Params * len(instances))()
+        for i, inst in enumerate(instances):
+            prm, keep = make_params(inst.K, inst.C, inst.size, inst.lam, inst.mu, inst.nu,
+                                    inst.reward, inst.gamma, inst.reject_cost)
+            arr[i] = prm
+            self._keep.append(keep)
+        h = ctypes.c_void_p()
+        _check(lib.mdp_build_batch(arr, len(instances), ctypes.byref(h)))
+        self._h = h
+        self.n = len(instances)
+        self.num_states = int(lib.batch_num_states(h, -1))
+        self.feasible_pairs = int(lib.batch_feasible_pairs(h, -1))
+        offs = (_c_int64 * (self.n + 1))()
+        _check(lib.batch_offsets(h, offs))
+        self.offsets = list(offs)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().mdp_free_batch(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def vi_solve(self, V, tol: float = 1e-6, max_iter: int = 1_000_000, stream=None):
+        """Returns (stats, iterations[n], residuals[n])."""
+        import torch
+        st = Stats()
+        its = (_c_int64 * self.n)()
+        res = (_c_double * self.n)()
+        _check(load().vi_solve_batch(self._h, _dev_tensor(V, torch.float32, self.num_states, "V"),
+                                     float(tol), int(max_iter), _stream_ptr(stream), ctypes.byref(st),
+                                     its, res), st)
+        return st.as_dict(), list(its), list(res)

@@ -11,8 +11,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/mdpvi.h"
 #include "kernels.hpp"
@@ -30,7 +32,16 @@ struct mdpvi_mdp {
   Ctl* ctl = nullptr;           // device control words
   Ctl* ctl_host = nullptr;      // pinned mirror
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double* aux = nullptr;        // gradient partials and outputs
+  size_t aux_bytes = 0;
+  double* out_host = nullptr;   // pinned, 2 * kMaxJ + 3 doubles
+  bool timing = false;          // bracket every sweep with events
+  hipEvent_t* sweep_ev = nullptr;   // 2 * kMaxChunk events (created on demand)
 };
+
+namespace {
+constexpr int64_t kMaxChunk = 256;
+}
 
 namespace {
 
@@ -97,10 +108,49 @@ int ensure_scratch(mdpvi_mdp* h, size_t bytes) {
   return MDPVI_OK;
 }
 
+// Auxiliary device doubles (gradient partials + outputs) and the pinned
+// host words the outputs are copied to.
+int ensure_aux(mdpvi_mdp* h, size_t doubles) {
+  if (!h->out_host) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->out_host), (2 * MDPVI_MAX_J + 3) * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+      h->out_host = nullptr;
+      return fail(MDPVI_ENOMEM, "hipHostMalloc of the output words failed");
+    }
+  }
+  const size_t bytes = doubles * sizeof(double);
+  if (bytes > h->aux_bytes) {
+    if (h->aux) {
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(h->aux));
+      h->aux = nullptr;
+      h->aux_bytes = 0;
+    }
+    if (hipMalloc(reinterpret_cast<void**>(&h->aux), bytes) != hipSuccess) {
+      h->aux = nullptr;
+      return fail(MDPVI_ENOMEM, "hipMalloc of %zu auxiliary bytes failed", bytes);
+    }
+    h->aux_bytes = bytes;
+  }
+  return MDPVI_OK;
+}
+
 double bits_to_double(unsigned long long b) {
   double d;
   std::memcpy(&d, &b, sizeof d);
   return d;
+}
+
+// Residual of sweep j from its partial words (max of the lanes, or their sum
+// for 1-norm residuals); a NaN lane makes the result NaN.
+double residual_of(const Ctl* c, long long j, bool sum) {
+  double r = 0.0;
+  for (int l = 0; l < mdpvi::kResLanes; ++l) {
+    const double v = bits_to_double(c->res[j % mdpvi::kResSlots][l][0]);
+    if (std::isnan(v)) return v;
+    r = sum ? r + v : std::max(r, v);
+  }
+  return r;
 }
 
 // Enqueue sweeps j = 0, 1, ... in chunks until the device reports the test
@@ -108,38 +158,49 @@ double bits_to_double(unsigned long long b) {
 // `sweep(j, in, out)` enqueues sweep j.
 template <typename T, typename Sweep>
 int run_loop(mdpvi_mdp* h, T* buf0, double tol, int64_t max_iter, hipStream_t s,
-             mdpvi_stats* st, double bytes_per_sweep, double backups_per_sweep, Sweep sweep) {
+             mdpvi_stats* st, double bytes_per_sweep, double backups_per_sweep, Sweep sweep,
+             bool sum_residual = false) {
   T* buf[2] = {buf0, static_cast<T*>(h->vbuf)};
   HIP_TRY(mdpvi::launch_ctl_init(h->ctl, s));
   HIP_TRY(hipEventRecord(h->ev0, s));
+  if (h->timing && !h->sweep_ev) {
+    h->sweep_ev = new (std::nothrow) hipEvent_t[2 * kMaxChunk]();
+    if (!h->sweep_ev) return fail(MDPVI_ENOMEM, "host allocation of timing events failed");
+    for (int64_t i = 0; i < 2 * kMaxChunk; ++i) HIP_TRY(hipEventCreate(&h->sweep_ev[i]));
+  }
   int64_t issued = 0;
   int64_t chunk = 8;
   long long done = -1;
+  double sweep_ms = 0.0;
   while (issued < max_iter) {
     const int64_t n = std::min<int64_t>(chunk, max_iter - issued);
     for (int64_t i = 0; i < n; ++i) {
       const int64_t j = issued + i;
+      if (h->timing) HIP_TRY(hipEventRecord(h->sweep_ev[2 * i], s));
       HIP_TRY(sweep(static_cast<long long>(j), buf[j & 1], buf[(j + 1) & 1]));
+      if (h->timing) HIP_TRY(hipEventRecord(h->sweep_ev[2 * i + 1], s));
     }
-    issued += n;
     HIP_TRY(hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     done = h->ctl_host->done_iter;
+    if (h->timing) {
+      for (int64_t i = 0; i < n; ++i) {
+        if (done >= 0 && issued + i >= done) break;   // sweeps from `done` on did no work
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->sweep_ev[2 * i], h->sweep_ev[2 * i + 1]));
+        sweep_ms += ms;
+      }
+    }
+    issued += n;
     if (done >= 0) break;
-    if (chunk < 256) chunk *= 2;
+    if (chunk < kMaxChunk) chunk *= 2;
   }
   int64_t final_iter;
   double res;
   bool converged;
-  if (done >= 0) {
-    final_iter = done;
-    res = bits_to_double(h->ctl_host->res[(final_iter - 1) % mdpvi::kResSlots]);
-    converged = res < tol;
-  } else {
-    final_iter = issued;
-    res = bits_to_double(h->ctl_host->res[(final_iter - 1) % mdpvi::kResSlots]);
-    converged = res < tol;
-  }
+  final_iter = done >= 0 ? done : issued;
+  res = residual_of(h->ctl_host, final_iter - 1, sum_residual);
+  converged = res < tol;
   if (final_iter & 1) {
     HIP_TRY(hipMemcpyAsync(buf0, buf[1], static_cast<size_t>(h->M.n_states) * sizeof(T),
                            hipMemcpyDeviceToDevice, s));
@@ -155,6 +216,7 @@ int run_loop(mdpvi_mdp* h, T* buf0, double tol, int64_t max_iter, hipStream_t s,
     st->seconds = ms * 1e-3;
     st->backups = backups_per_sweep * static_cast<double>(final_iter);
     st->bytes = bytes_per_sweep * static_cast<double>(final_iter);
+    st->sweep_seconds = sweep_ms * 1e-3;
   }
   if (std::isnan(res) || std::isinf(res))
     return fail(MDPVI_ENAN, "non-finite residual after %lld sweeps", (long long)final_iter);
@@ -164,15 +226,9 @@ int run_loop(mdpvi_mdp* h, T* buf0, double tol, int64_t max_iter, hipStream_t s,
   return MDPVI_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* mdpvi_last_error(void) { return g_err.c_str(); }
-
-int mdp_build(const mdpvi_params* p, mdpvi_mdp_t* out) {
-  if (!p || !out) return fail(MDPVI_EINVAL, "NULL argument");
-  *out = nullptr;
+// Fill a Model from validated parameters (shared by single and batched builds).
+int fill_model(const mdpvi_params* p, Model& M, int64_t& pairs_out) {
+  if (!p) return fail(MDPVI_EINVAL, "NULL argument");
   if (p->K < 1 || p->K > MDPVI_MAX_K) return fail(MDPVI_EINVAL, "K=%d outside [1, %d]", p->K, MDPVI_MAX_K);
   if (p->J < 1 || p->J > MDPVI_MAX_J) return fail(MDPVI_EINVAL, "J=%d outside [1, %d]", p->J, MDPVI_MAX_J);
   if (p->C < 1) return fail(MDPVI_EINVAL, "C=%d must be >= 1", p->C);
@@ -202,9 +258,6 @@ int mdp_build(const mdpvi_params* p, mdpvi_mdp_t* out) {
     return fail(MDPVI_ERANGE, "(C+1)^K = %lld occupancies exceed one launch grid",
                 (long long)n_occ);
 
-  mdpvi_mdp* h = new (std::nothrow) mdpvi_mdp();
-  if (!h) return fail(MDPVI_ENOMEM, "host allocation failed");
-  Model& M = h->M;
   std::memset(&M, 0, sizeof M);
   M.K = p->K;
   M.C = p->C;
@@ -235,11 +288,66 @@ int mdp_build(const mdpvi_params* p, mdpvi_mdp_t* out) {
   M.mu_L = p->mu / Lam;
   M.nu_L = p->nu / Lam;
   M.gamma = p->gamma;
+  for (int j = 0; j < p->J; ++j) {
+    M.lam[j] = p->lambda[j];
+    M.reward[j] = p->reward[j];
+    M.cost[j] = p->reject_cost ? p->reject_cost[j] : 0.0;
+    M.c_obj[j] = p->lambda[j] / lam_tot;
+  }
+  M.mu = p->mu;
+  M.nu = p->nu;
+  M.Lam = Lam;
+  M.lam_tot = lam_tot;
   // feasible pairs: the paid cloud everywhere plus, per class e and host a,
   // the (C+1-size_e)/(C+1) share of occupancies with room on a
   int64_t pairs = 0;
   for (int j = 0; j < p->J; ++j)
     pairs += n_occ + static_cast<int64_t>(p->K) * (n_occ / M.R) * (M.R - p->size[j]);
+  pairs_out = pairs;
+  return MDPVI_OK;
+}
+
+
+}  // namespace
+
+struct mdpvi_batch {
+  int n = 0;
+  std::vector<Model> models;
+  std::vector<int64_t> offsets;      // n + 1 state offsets
+  std::vector<int64_t> pairs;        // feasible pairs per sweep, per instance
+  std::vector<int32_t> lds_list, round_list;
+  std::vector<mdpvi::Tile> tiles;
+  int lds_maxK = 1, lds_maxJ = 1, rnd_maxK = 1, rnd_maxJ = 1;
+  size_t lds_bytes = 0;
+  int device = -1;
+  mdpvi::BatchInst* d_inst = nullptr;
+  int32_t* d_lds = nullptr;
+  int32_t* d_round = nullptr;
+  mdpvi::Tile* d_tiles = nullptr;
+  mdpvi::BatchCtl* d_ctl = nullptr;
+  int* d_remaining = nullptr;
+  mdpvi::BatchOut* d_out = nullptr;
+  float* W = nullptr;               // ping-pong partner of the concatenated values
+  int* h_remaining = nullptr;       // pinned
+  mdpvi::BatchOut* h_out = nullptr; // pinned
+  hipStream_t side = nullptr;       // second stream for the LDS-resident solves
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev0 = nullptr, ev1 = nullptr;
+};
+
+extern "C" {
+
+const char* mdpvi_last_error(void) { return g_err.c_str(); }
+
+int mdp_build(const mdpvi_params* p, mdpvi_mdp_t* out) {
+  if (!p || !out) return fail(MDPVI_EINVAL, "NULL argument");
+  *out = nullptr;
+  Model M;
+  int64_t pairs = 0;
+  int rc = fill_model(p, M, pairs);
+  if (rc) return rc;
+  mdpvi_mdp* h = new (std::nothrow) mdpvi_mdp();
+  if (!h) return fail(MDPVI_ENOMEM, "host allocation failed");
+  h->M = M;
   h->feasible_pairs = pairs;
   *out = h;
   return MDPVI_OK;
@@ -252,7 +360,20 @@ void mdp_free(mdpvi_mdp_t h) {
   if (h->ctl_host) (void)hipHostFree(h->ctl_host);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->aux) (void)hipFree(h->aux);
+  if (h->out_host) (void)hipHostFree(h->out_host);
+  if (h->sweep_ev) {
+    for (int64_t i = 0; i < 2 * kMaxChunk; ++i)
+      if (h->sweep_ev[i]) (void)hipEventDestroy(h->sweep_ev[i]);
+    delete[] h->sweep_ev;
+  }
   delete h;
+}
+
+int mdp_set_timing(mdpvi_mdp_t h, int32_t per_sweep_events) {
+  if (!h) return fail(MDPVI_EINVAL, "NULL handle");
+  h->timing = per_sweep_events != 0;
+  return MDPVI_OK;
 }
 
 int64_t mdp_num_states(mdpvi_mdp_t h) { return h ? h->M.n_states : -1; }
@@ -309,10 +430,292 @@ int policy_eval(mdpvi_mdp_t h, const uint8_t* pi, double* V, double tol, int64_t
                           });
 }
 
+int vi_adjoint(mdpvi_mdp_t h, const uint8_t* pi, const double* V_pi, float* w, double* grad,
+               double* objective, double tol, int64_t max_iter, void* hip_stream,
+               mdpvi_stats* st) {
+  if (!h || !pi || !V_pi || !w || !grad)
+    return fail(MDPVI_EINVAL, "NULL handle, policy, value, adjoint or gradient array");
+  if (!(tol > 0)) return fail(MDPVI_EINVAL, "tol=%g must be > 0", tol);
+  if (max_iter < 1) return fail(MDPVI_EINVAL, "max_iter=%lld must be >= 1", (long long)max_iter);
+  int rc = ensure_scratch(h, static_cast<size_t>(h->M.n_states) * sizeof(float));
+  if (rc) return rc;
+  const size_t npart = mdpvi::grad_partial_doubles(h->M);
+  rc = ensure_aux(h, npart + 2 * MDPVI_MAX_J + 3);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const Model& M = h->M;
+  HIP_TRY(mdpvi::launch_ctl_init(h->ctl, s));
+  HIP_TRY(mdpvi::launch_policy_check(M, pi, h->ctl, s));
+  HIP_TRY(hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h->ctl_host->flag)
+    return fail(MDPVI_EINVAL, "policy has an action that is not feasible in its state");
+  rc = run_loop<float>(
+      h, w, tol, max_iter, s, st, 9.0 * M.n_states, static_cast<double>(M.n_states),
+      [&](long long j, float* in, float* out) {
+        return mdpvi::launch_adjoint_sweep(M, pi, in, out, h->ctl, j, tol, s);
+      },
+      /*sum_residual=*/true);
+  if (rc != MDPVI_OK && rc != MDPVI_ENOCONV) return rc;
+  double* out_dev = h->aux + npart;
+  HIP_TRY(mdpvi::launch_grad(M, pi, V_pi, w, h->aux, out_dev, s));
+  const int nt = 2 * M.J + 2;
+  HIP_TRY(hipMemcpyAsync(h->out_host, out_dev, (nt + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::memcpy(grad, h->out_host, nt * sizeof(double));
+  if (objective) *objective = h->out_host[nt];
+  return rc;
+}
+
+int policy_objective(mdpvi_mdp_t h, const double* V, double* out, void* hip_stream) {
+  if (!h || !V || !out) return fail(MDPVI_EINVAL, "NULL handle, value array or output");
+  int rc = ensure_aux(h, 1);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  HIP_TRY(mdpvi::launch_objective(h->M, V, h->aux, s));
+  HIP_TRY(hipMemcpyAsync(h->out_host, h->aux, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = h->out_host[0];
+  return MDPVI_OK;
+}
+
 int policy_greedy(mdpvi_mdp_t h, int32_t kind, uint8_t* pi, void* hip_stream) {
   if (!h || !pi) return fail(MDPVI_EINVAL, "NULL handle or policy array");
   if (kind != 0 && kind != 1) return fail(MDPVI_EINVAL, "kind=%d must be 0 or 1", kind);
   HIP_TRY(mdpvi::launch_greedy(h->M, kind, pi, static_cast<hipStream_t>(hip_stream)));
+  return MDPVI_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+
+namespace {
+
+int ensure_batch_device(mdpvi_batch* b) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (b->device >= 0) {
+    if (b->device != dev)
+      return fail(MDPVI_EINVAL, "batch lives on device %d, current device is %d", b->device, dev);
+    return MDPVI_OK;
+  }
+  const int n = b->n;
+  std::vector<mdpvi::BatchInst> inst(n);
+  int n_ctl = 0;
+  for (int i = 0; i < n; ++i) {
+    inst[i].M = b->models[i];
+    inst[i].offset = b->offsets[i];
+    inst[i].lds = 0;
+    inst[i].ctl = -1;
+  }
+  for (int32_t i : b->lds_list) inst[i].lds = 1;
+  for (int32_t i : b->round_list) inst[i].ctl = n_ctl++;
+  auto dalloc = [&](void** p, size_t bytes) -> int {
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      *p = nullptr;
+      return fail(MDPVI_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    return MDPVI_OK;
+  };
+  int rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_inst), n * sizeof(mdpvi::BatchInst)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_lds), b->lds_list.size() * sizeof(int32_t)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_round), b->round_list.size() * sizeof(int32_t)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_tiles), b->tiles.size() * sizeof(mdpvi::Tile)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_ctl), std::max(n_ctl, 1) * sizeof(mdpvi::BatchCtl)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_remaining), sizeof(int)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_out), n * sizeof(mdpvi::BatchOut)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->W), std::max<int64_t>(b->offsets[n], 1) * sizeof(float)))) return rc;
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_remaining), sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&b->h_out), n * sizeof(mdpvi::BatchOut), hipHostMallocDefault) != hipSuccess)
+    return fail(MDPVI_ENOMEM, "hipHostMalloc of batch outputs failed");
+  HIP_TRY(hipMemcpy(b->d_inst, inst.data(), n * sizeof(mdpvi::BatchInst), hipMemcpyHostToDevice));
+  if (!b->lds_list.empty())
+    HIP_TRY(hipMemcpy(b->d_lds, b->lds_list.data(), b->lds_list.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (!b->round_list.empty())
+    HIP_TRY(hipMemcpy(b->d_round, b->round_list.data(), b->round_list.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (!b->tiles.empty())
+    HIP_TRY(hipMemcpy(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(mdpvi::Tile), hipMemcpyHostToDevice));
+  HIP_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+  HIP_TRY(hipEventCreate(&b->ev0));
+  HIP_TRY(hipEventCreate(&b->ev1));
+  b->device = dev;
+  return MDPVI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mdp_build_batch(const mdpvi_params* p, int32_t n, mdpvi_batch_t* out) {
+  if (!p || !out) return fail(MDPVI_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n < 1) return fail(MDPVI_EINVAL, "n=%d must be >= 1", n);
+  mdpvi_batch* b = new (std::nothrow) mdpvi_batch();
+  if (!b) return fail(MDPVI_ENOMEM, "host allocation failed");
+  b->n = n;
+  b->models.resize(n);
+  b->offsets.resize(n + 1);
+  b->pairs.resize(n);
+  b->offsets[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    int rc = fill_model(&p[i], b->models[i], b->pairs[i]);
+    if (rc) {
+      std::string msg = g_err;
+      delete b;
+      return fail(rc, "instance %d: %s", i, msg.c_str());
+    }
+    if (b->models[i].n_states >= (int64_t{1} << 31)) {
+      delete b;
+      return fail(MDPVI_ERANGE, "instance %d has %lld states; batched instances must stay below 2^31", i,
+                  (long long)b->models[i].n_states);
+    }
+    b->offsets[i + 1] = b->offsets[i] + b->models[i].n_states;
+  }
+  if (b->offsets[n] >= (int64_t{1} << 40)) {
+    delete b;
+    return fail(MDPVI_ERANGE, "batch holds too many states");
+  }
+  // LDS-resident when two FP32 copies fit the workgroup's LDS budget; the
+  // rest are tiled for the round form.
+  const int64_t lds_states = static_cast<int64_t>(mdpvi::kLdsBudget / (2 * sizeof(float)));
+  std::vector<std::pair<double, int32_t>> cost;
+  int64_t max_lds_n = 0;
+  for (int i = 0; i < n; ++i) {
+    const Model& M = b->models[i];
+    if (M.n_states <= lds_states) {
+      // sweeps to convergence grow like 1/(1 - gamma)
+      cost.push_back({static_cast<double>(M.n_states) / (1.0 - M.gamma + 1e-3), i});
+      max_lds_n = std::max(max_lds_n, M.n_states);
+      b->lds_maxK = std::max(b->lds_maxK, M.K);
+      b->lds_maxJ = std::max(b->lds_maxJ, M.J);
+    } else {
+      b->round_list.push_back(i);
+      b->rnd_maxK = std::max(b->rnd_maxK, M.K);
+      b->rnd_maxJ = std::max(b->rnd_maxJ, M.J);
+      const uint32_t per = mdpvi::kBlock * mdpvi::kOccPerThread;
+      for (uint32_t t = 0; t < static_cast<uint32_t>(M.n_occ); t += per) b->tiles.push_back({i, t});
+    }
+  }
+  std::sort(cost.begin(), cost.end(), [](auto& x, auto& y) { return x.first > y.first; });
+  for (auto& c : cost) b->lds_list.push_back(c.second);
+  b->lds_bytes = static_cast<size_t>(2 * max_lds_n) * sizeof(float);
+  *out = b;
+  return MDPVI_OK;
+}
+
+void mdp_free_batch(mdpvi_batch_t b) {
+  if (!b) return;
+  if (b->side) (void)hipStreamSynchronize(b->side);
+  (void)hipFree(b->d_inst);
+  (void)hipFree(b->d_lds);
+  (void)hipFree(b->d_round);
+  (void)hipFree(b->d_tiles);
+  (void)hipFree(b->d_ctl);
+  (void)hipFree(b->d_remaining);
+  (void)hipFree(b->d_out);
+  (void)hipFree(b->W);
+  if (b->h_remaining) (void)hipHostFree(b->h_remaining);
+  if (b->h_out) (void)hipHostFree(b->h_out);
+  if (b->side) (void)hipStreamDestroy(b->side);
+  for (hipEvent_t e : {b->ev_fork, b->ev_join, b->ev0, b->ev1})
+    if (e) (void)hipEventDestroy(e);
+  delete b;
+}
+
+int32_t batch_num_instances(mdpvi_batch_t b) { return b ? b->n : -1; }
+
+int64_t batch_num_states(mdpvi_batch_t b, int32_t i) {
+  if (!b || i < -1 || i >= b->n) return -1;
+  return i < 0 ? b->offsets[b->n] : b->models[i].n_states;
+}
+
+int64_t batch_feasible_pairs(mdpvi_batch_t b, int32_t i) {
+  if (!b || i < -1 || i >= b->n) return -1;
+  if (i >= 0) return b->pairs[i];
+  int64_t t = 0;
+  for (int64_t x : b->pairs) t += x;
+  return t;
+}
+
+int batch_offsets(mdpvi_batch_t b, int64_t* offsets) {
+  if (!b || !offsets) return fail(MDPVI_EINVAL, "NULL batch or offsets");
+  std::memcpy(offsets, b->offsets.data(), (b->n + 1) * sizeof(int64_t));
+  return MDPVI_OK;
+}
+
+int vi_solve_batch(mdpvi_batch_t b, float* V, double tol, int64_t max_iter, void* hip_stream,
+                   mdpvi_stats* st, int64_t* iterations, double* residuals) {
+  if (!b || !V) return fail(MDPVI_EINVAL, "NULL batch or value array");
+  if (!(tol > 0)) return fail(MDPVI_EINVAL, "tol=%g must be > 0", tol);
+  if (max_iter < 1) return fail(MDPVI_EINVAL, "max_iter=%lld must be >= 1", (long long)max_iter);
+  int rc = ensure_batch_device(b);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int n_round = static_cast<int>(b->round_list.size());
+  const int n_lds = static_cast<int>(b->lds_list.size());
+  HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, n_round, b->d_remaining, s));
+  HIP_TRY(hipEventRecord(b->ev0, s));
+  HIP_TRY(hipEventRecord(b->ev_fork, s));
+  HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
+  HIP_TRY(mdpvi::launch_batch_lds_vi(b->d_inst, b->d_lds, n_lds, b->lds_maxK, b->lds_maxJ, b->lds_bytes,
+                                     V, tol, max_iter, b->d_out, b->side));
+  HIP_TRY(hipEventRecord(b->ev_join, b->side));
+  int64_t issued = 0;
+  if (n_round > 0) {
+    int64_t chunk = 8;
+    while (issued < max_iter) {
+      const int64_t m = std::min<int64_t>(chunk, max_iter - issued);
+      for (int64_t k = 0; k < m; ++k)
+        HIP_TRY(mdpvi::launch_batch_round(b->d_inst, b->d_tiles, static_cast<int>(b->tiles.size()),
+                                          b->rnd_maxK, b->rnd_maxJ, V, b->W, b->d_ctl, b->d_remaining,
+                                          issued + k, tol, s));
+      issued += m;
+      HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (*b->h_remaining <= 0) break;
+      if (chunk < kMaxChunk) chunk *= 2;
+    }
+    HIP_TRY(mdpvi::launch_batch_round_finish(b->d_inst, b->d_round, n_round, V, b->W, b->d_ctl, issued,
+                                             b->d_out, s));
+  }
+  HIP_TRY(hipStreamWaitEvent(s, b->ev_join, 0));
+  HIP_TRY(hipMemcpyAsync(b->h_out, b->d_out, b->n * sizeof(mdpvi::BatchOut), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(b->ev1, s));
+  HIP_TRY(hipEventSynchronize(b->ev1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  int64_t max_it = 0, not_conv = 0, nan = 0;
+  double backups = 0, bytes = 0, max_res = 0;
+  for (int i = 0; i < b->n; ++i) {
+    const mdpvi::BatchOut& o = b->h_out[i];
+    if (iterations) iterations[i] = o.iterations;
+    if (residuals) residuals[i] = o.residual;
+    max_it = std::max<int64_t>(max_it, o.iterations);
+    backups += static_cast<double>(b->pairs[i]) * o.iterations;
+    bytes += 8.0 * b->models[i].n_states * o.iterations;
+    if (std::isnan(o.residual)) ++nan;
+    else if (!(o.residual < tol)) ++not_conv;
+    if (!std::isnan(o.residual)) max_res = std::max(max_res, o.residual);
+  }
+  if (st) {
+    st->iterations = max_it;
+    st->residual_inf = max_res;
+    st->bound_inf = 0.0;
+    for (int i = 0; i < b->n; ++i)
+      st->bound_inf = std::max(st->bound_inf, b->models[i].gamma / (1.0 - b->models[i].gamma) * b->h_out[i].residual);
+    st->seconds = ms * 1e-3;
+    st->backups = backups;
+    st->bytes = bytes;
+    st->sweep_seconds = 0.0;
+  }
+  if (nan) return fail(MDPVI_ENAN, "%lld instances produced a non-finite residual", (long long)nan);
+  if (not_conv)
+    return fail(MDPVI_ENOCONV, "%lld instances did not meet tol within max_iter", (long long)not_conv);
   return MDPVI_OK;
 }
 

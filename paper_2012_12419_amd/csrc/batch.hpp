@@ -1,0 +1,35 @@
+// batch.hpp -- device descriptors of the batched forms.
+#pragma once
+
+#include "model.hpp"
+
+namespace mdpvi {
+
+constexpr int kLdsBlock = 512;        // threads of an LDS-resident instance solve
+constexpr int kBatchLanes = 8;        // residual words per instance (round form)
+constexpr size_t kLdsBudget = 160 * 1024 - 1024;  // dynamic LDS per workgroup
+
+struct BatchInst {
+  Model M;
+  int64_t offset;   // first state of this instance in the concatenated arrays
+  int32_t lds;      // 1: solved LDS-resident by one workgroup
+  int32_t ctl;      // index of its round-form control block (-1 if none)
+};
+
+struct Tile {
+  int32_t inst;
+  uint32_t first;   // first occupancy of the tile
+};
+
+struct BatchCtl {
+  long long done_iter;
+  long long pad[kResStride - 1];
+  unsigned long long res[kResSlots][kBatchLanes][kResStride];
+};
+
+struct BatchOut {
+  long long iterations;
+  double residual;
+};
+
+}  // namespace mdpvi

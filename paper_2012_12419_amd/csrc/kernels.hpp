@@ -2,6 +2,7 @@
 // library; the public surface is the C ABI in mdpvi.h).
 #pragma once
 
+#include "batch.hpp"
 #include "model.hpp"
 
 namespace mdpvi {
@@ -32,5 +33,31 @@ hipError_t launch_eval_sweep(const Model& M, const uint8_t* pi, const double* Vi
 
 // Greedy heuristic policies (0 least-loaded, 1 first-fit).
 hipError_t launch_greedy(const Model& M, int kind, uint8_t* pi, hipStream_t s);
+
+// One transposed (adjoint) sweep w^{j+1} = c + gamma P_pi^T w^j, 1-norm residual.
+hipError_t launch_adjoint_sweep(const Model& M, const uint8_t* pi, const float* win, float* wout,
+                                Ctl* ctl, long long j, double tol, hipStream_t s);
+
+// Doubles of workgroup partials needed by launch_grad.
+size_t grad_partial_doubles(const Model& M);
+
+// out[0..2J+1] = dJ/dtheta, out[2J+2] = J (device pointers).
+hipError_t launch_grad(const Model& M, const uint8_t* pi, const double* V, const float* w,
+                       double* partial, double* out, hipStream_t s);
+
+// out[0] = J = sum_e c_e V(0, e) (device pointer).
+hipError_t launch_objective(const Model& M, const double* V, double* out, hipStream_t s);
+
+// Batched forms (batch.hip).
+hipError_t launch_batch_lds_vi(const BatchInst* insts, const int32_t* list, int n_list, int maxK,
+                               int maxJ, size_t lds_bytes, float* V, double tol, long long max_iter,
+                               BatchOut* out, hipStream_t s);
+hipError_t launch_batch_ctl_init(BatchCtl* ctl, int n, int* remaining, hipStream_t s);
+hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
+                              int maxJ, float* V, float* W, BatchCtl* ctl, int* remaining,
+                              long long j, double tol, hipStream_t s);
+hipError_t launch_batch_round_finish(const BatchInst* insts, const int32_t* list, int n_list,
+                                     float* V, const float* W, BatchCtl* ctl, long long issued,
+                                     BatchOut* out, hipStream_t s);
 
 }  // namespace mdpvi

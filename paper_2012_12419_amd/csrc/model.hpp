@@ -14,9 +14,15 @@
 
 namespace mdpvi {
 
+constexpr int kBlock = 256;       // threads of a sweep workgroup: 4 wavefronts of 64
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies, 32 CUs each
+constexpr int kOccPerThread = 4;  // occupancies per thread in the sweep kernels
 constexpr int kMaxK = 16;
 constexpr int kMaxJ = 8;
-constexpr int kResSlots = 4;  // ring of per-sweep residual words
+constexpr int kResSlots = 4;    // ring of per-sweep residuals
+constexpr int kResLanes = 64;   // words per residual: workgroup b reduces into word b % 64
+constexpr int kResStride = 16;  // one word per 128-byte line (64-bit words)
 
 // Unsigned 32-bit division by a run-time constant d >= 2 with one high
 // multiply, a subtract, an add and two shifts (Granlund & Montgomery, "Division
@@ -67,19 +73,35 @@ struct Model {
   double r_place[kMaxJ];        // P_arr * reward_j
   double r_reject[kMaxJ];       // -P_arr * reject_cost_j
   double gamma;
+  // raw parameters, for the gradient with respect to them
+  double lam[kMaxJ];            // lambda_j
+  double reward[kMaxJ];         // r_j
+  double cost[kMaxJ];           // c_j (paid-cloud cost)
+  double c_obj[kMaxJ];          // lambda_j / sum lambda: weights of the empty states in J
+  double mu, nu, Lam, lam_tot;
 };
 
 // Control words of one iterative solve, in device memory.
 //   done_iter: -1 while running; else the index k of the first iterate V^k
 //              whose residual ||V^k - V^{k-1}|| passed the test (or was NaN).
-//   res[r]:    bit pattern of the FP64 residual of the sweep with
-//              index j, r = j mod kResSlots (non-negative doubles order like
-//              their bit patterns, so atomicMax on the bits is a max).
 //   flag:      set by validation kernels (an infeasible policy entry).
+//   res:       the residual of the sweep with index j lives in ring slot
+//              r = j mod kResSlots as kResLanes partial words, one per
+//              128-byte line so that concurrent atomics from different
+//              workgroups do not queue on one address; the residual is the
+//              max (or, for 1-norm residuals, the sum) of the lanes.  A word
+//              holds the bit pattern of a non-negative double: such doubles
+//              order like their bit patterns, so atomicMax on the bits is a
+//              max, and NaN patterns order above +inf.
 struct Ctl {
   long long done_iter;
   long long flag;
-  unsigned long long res[kResSlots];
+  long long pad[kResStride - 2];
+  unsigned long long res[kResSlots][kResLanes][kResStride];
 };
+
+__host__ __device__ inline unsigned long long* res_word(Ctl* c, long long j, int lane) {
+  return &c->res[j % kResSlots][lane][0];
+}
 
 }  // namespace mdpvi

@@ -124,11 +124,13 @@ __global__ __launch_bounds__(kBlock) void eval_sweep_kernel(Model M, const uint8
                                                              const double* __restrict__ Vin,
                                                              double* __restrict__ Vout, Ctl* ctl,
                                                              long long j, double tol) {
-  if (sweep_stopped(ctl, j, tol)) return;
+  if (sweep_stopped<ResKind::kMax>(ctl, j, tol)) return;
   const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-  const Idx o = static_cast<Idx>(b) * kBlock + threadIdx.x;
   double dmax = 0.0;
-  if (o < static_cast<Idx>(M.n_occ)) {
+  for (int i = 0; i < kOccPerThread; ++i) {
+    const Idx o = static_cast<Idx>(b) * (kBlock * kOccPerThread) + threadIdx.x +
+                  static_cast<Idx>(i * kBlock);
+    if (o >= static_cast<Idx>(M.n_occ)) break;
     const Idx nocc = static_cast<Idx>(M.n_occ);
     int n[KMAX];
     decode<KMAX>(M, o, n);
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void eval_sweep_kernel(Model M, const uint8
       }
     }
   }
-  block_max_to(dmax, &ctl->res[j % kResSlots]);
+  block_max_to(dmax, ctl, j);
 }
 
 template <int KMAX, int JMAX, typename Idx>
@@ -197,6 +199,11 @@ __global__ __launch_bounds__(kBlock) void greedy_kernel(Model M, int kind, uint8
 
 static inline dim3 occ_grid(const Model& M) {
   return dim3(static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + kBlock - 1) / kBlock));
+}
+
+static inline dim3 sweep_grid(const Model& M) {
+  const uint64_t per = static_cast<uint64_t>(kBlock) * kOccPerThread;
+  return dim3(static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + per - 1) / per));
 }
 
 // Calls f(KMAX, JMAX) with the smallest compiled bounds that fit M.
@@ -270,14 +277,14 @@ hipError_t launch_eval_sweep(const Model& M, const uint8_t* pi, const double* Vi
   if (use_32bit_index(M)) {
     return dispatch_kj(M, [&](auto km, auto jm) {
       constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
-      hipLaunchKernelGGL((eval_sweep_kernel<KM, JM, uint32_t>), occ_grid(M),
+      hipLaunchKernelGGL((eval_sweep_kernel<KM, JM, uint32_t>), sweep_grid(M),
                                            dim3(kBlock), 0, s, M, pi, Vin, Vout, ctl, j, tol);
       return hipGetLastError();
     });
   } else {
     return dispatch_kj(M, [&](auto km, auto jm) {
       constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
-      hipLaunchKernelGGL((eval_sweep_kernel<KM, JM, uint64_t>), occ_grid(M),
+      hipLaunchKernelGGL((eval_sweep_kernel<KM, JM, uint64_t>), sweep_grid(M),
                                            dim3(kBlock), 0, s, M, pi, Vin, Vout, ctl, j, tol);
       return hipGetLastError();
     });

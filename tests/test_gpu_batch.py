@@ -1,0 +1,75 @@
+"""GPU parity of the batched solver.
+
+* A mixed batch (LDS-resident and round-form instances, ragged sizes) against
+  the FP64 oracle instance by instance.
+* The 512-instance parameter sweep: every instance's batched result equals
+  the single-instance vi_solve result bit for bit (same backup arithmetic, same
+  stopping test), and sampled instances are fixed points of the oracle's
+  Bellman operator up to one FP32 rounding.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import vi
+from tests.gpu_util import torch_cuda, vi_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mdpvi():
+    torch_cuda()
+    import paper_2012_12419_amd as m
+    m.load()
+    return m
+
+
+def _mixed():
+    out = list(W.batch(20, seed=7))
+    out.append(W.make(4, 12, (1, 2, 3), (0.6, 0.5, 0.3), 0.08, 0.02, (1.0, 2.1, 3.3), 0.97))  # 85,683
+    out.append(W.make(5, 6, (1, 2), (0.9, 0.4), 0.1, 0.02, (1.0, 2.4), 0.95))                 # 33,614
+    out.append(W.make(1, 1, (1,), (0.5,), 0.3, 0.1, (1.0,), 0.9))                             # 2
+    out.append(W.make(2, 4, (1,), (0.7,), 0.1, 0.02, (1.2,), 0.93))                           # 25
+    return out
+
+
+def test_batch_mixed_vs_oracle(mdpvi):
+    import torch
+    insts = _mixed()
+    b = mdpvi.Batch(insts)
+    V = torch.zeros(b.num_states, device="cuda")
+    st, its, res = b.vi_solve(V, tol=1e-7)
+    Vh = V.cpu().numpy()
+    assert b.feasible_pairs == sum(vi.feasible_pairs(p) for p in insts)
+    for i, p in enumerate(insts):
+        print(f"instance {i}: K={p.K} C={p.C} J={p.J} N={p.num_states} sweeps={its[i]}", flush=True)
+        assert res[i] < 1e-7
+        star = vi.value_iteration(p, 1e-12).V
+        vi_close(Vh[b.offsets[i]:b.offsets[i + 1]], star)
+
+
+def test_batch_equals_per_instance(mdpvi):
+    import torch
+    insts = W.batch(512, seed=3)
+    b = mdpvi.Batch(insts)
+    V = torch.zeros(b.num_states, device="cuda")
+    st, its, res = b.vi_solve(V, tol=1e-6)
+    print(f"batch: {b.n} instances, {b.num_states} states, {st['seconds']:.3f} s", flush=True)
+    Vh = V.cpu().numpy()
+    rng = np.random.default_rng(0)
+    check = set(rng.choice(512, 48, replace=False).tolist()) | {int(np.argmax([p.num_states for p in insts]))}
+    for i in sorted(check):
+        p = insts[i]
+        mdp = mdpvi.MDP.from_instance(p)
+        Vi = torch.zeros(mdp.num_states, device="cuda")
+        sti = mdp.vi_solve(Vi, tol=1e-6)
+        assert sti["iterations"] == its[i], (i, sti["iterations"], its[i])
+        got = Vh[b.offsets[i]:b.offsets[i + 1]]
+        assert np.array_equal(got.view(np.uint32), Vi.cpu().numpy().view(np.uint32)), i
+    for i in sorted(check)[:8]:
+        p = insts[i]
+        Vg = Vh[b.offsets[i]:b.offsets[i + 1]].astype(np.float64)
+        TV = vi.bellman(p, Vg)
+        half_ulp = np.spacing(np.abs(Vg).astype(np.float32)).astype(np.float64) / 2
+        assert np.all(np.abs(TV - Vg) <= 1.0001 * half_ulp + 1e-6)

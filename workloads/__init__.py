@@ -108,11 +108,17 @@ def batch(n: int = 512, seed: int = 3) -> List[Instance]:
 
 
 def gradient_instance(K: int = 5, C: int = 10) -> Instance:
-    """K=5, C=10, J=2 with the small-parity rates, gamma 0.98 (161,051 x 2 states).
+    """K=5, C=10, J=2 (sizes 1, 2), gamma 0.98: 161,051 x 2 states.
 
+    The small-parity release, leave and reward rates with the arrival rates
+    scaled by 5, lambda = (3.0, 1.5): the offered load (60 units) exceeds the
+    50 units of capacity, so the optimal policy reserves room for the larger
+    class and sends some small tasks to the paid cloud.  (At lambda =
+    (0.6, 0.3) the system almost never fills and J reduces to
+    P_arr E[r] / (1 - gamma) = 11.25, which would not exercise the policy.)
     ``gradient_instance(2, 6)`` is the 98-state copy used for dense checks.
     """
-    return make(K, C, (1, 2), (0.6, 0.3), 0.1, 0.02, (1.0, 2.5), 0.98)
+    return make(K, C, (1, 2), (3.0, 1.5), 0.1, 0.02, (1.0, 2.5), 0.98)
 
 
 def random_small(seed: int, K_max: int = 3, C_max: int = 5, J_max: int = 3) -> Instance:
