@@ -85,6 +85,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket sweeps with events (roofline fields become null)")
+    ap.add_argument("--sweep-form", type=int, default=-1,
+                    help="value-iteration sweep kernel: -1 automatic, 0 direct, t>0 LDS slab of t digits")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -107,6 +109,7 @@ def main() -> int:
     inst, desc = workload(args.workload)
     mdp = mdpvi.MDP.from_instance(inst)
     mdp.set_timing(not args.no_timing)
+    mdp.set_sweep_form(args.sweep_form)
     N = mdp.num_states
     dev = "cuda:0"
     V = torch.zeros(N, dtype=torch.float32, device=dev)
@@ -194,7 +197,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "states": N,
                    "feasible_pairs_per_sweep": mdp.feasible_pairs, "tol": args.tol,
-                   "eval_tol": args.eval_tol, "values": "FP32 storage, FP64 sums (VI); FP64 (evaluation)"},
+                   "eval_tol": args.eval_tol, "sweep_form": args.sweep_form,
+                   "values": "FP32 storage, FP64 sums (VI); FP64 (evaluation)"},
         "time_to_tol_s": t_tol,
         "vi_sweeps": vi_sweeps,
         "eval_sweeps": ev_sweeps,

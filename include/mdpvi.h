@@ -216,6 +216,53 @@ int vi_solve_batch(mdpvi_batch_t b, float *V, double tol, int64_t max_iter,
                    void *hip_stream, mdpvi_stats *st, int64_t *iterations,
                    double *residuals);
 
+/* Choice of the value-iteration sweep kernel for this handle (a tuning knob;
+ * every form computes bit-identical iterates).  slab_digits = -1: automatic
+ * (the default); 0: the direct form (every neighbour read from global
+ * memory); t > 0: the LDS slab form, each workgroup staging the (C+1)^t
+ * occupancies that share the high digits.  Errors: MDPVI_EINVAL (NULL
+ * handle, t >= K, or a slab that does not fit 64 KB of LDS).                */
+int mdp_set_sweep_form(mdpvi_mdp_t h, int32_t slab_digits);
+
+/* Batched extraction / greedy heuristic: as policy_extract(_f64) and
+ * policy_greedy for every instance, over the concatenated arrays (one
+ * launch over the tiles of all instances).  Asynchronous.                   */
+int policy_extract_batch(mdpvi_batch_t b, const float *V, uint8_t *pi, float *gap,
+                         void *hip_stream);
+int policy_extract_batch_f64(mdpvi_batch_t b, const double *V, uint8_t *pi, float *gap,
+                             void *hip_stream);
+int policy_greedy_batch(mdpvi_batch_t b, int32_t kind, uint8_t *pi, void *hip_stream);
+
+/* Batched policy_eval: V device double[total] in V^0, out each instance's V_pi
+ * (FP64 round-form sweeps, per-instance stopping test).  iterations and
+ * residuals: host arrays of n or NULL.  Errors: as policy_eval (EINVAL names
+ * the first instance with an infeasible action).                            */
+int policy_eval_batch(mdpvi_batch_t b, const uint8_t *pi, double *V, double tol,
+                      int64_t max_iter, void *hip_stream, mdpvi_stats *st,
+                      int64_t *iterations, double *residuals);
+
+/* Batched vi_adjoint.  w: device float[total] in w^0, out the adjoint weights.
+ * grad: host array of sum_i (2 J_i + 2) doubles, instance i's gradient
+ * (lambda_1..J_i, mu, nu, r_1..J_i) at offset sum_{k<i} (2 J_k + 2);
+ * objective: host double[n] (J of every instance) or NULL; iterations: host
+ * int64[n] or NULL.  Errors: as vi_adjoint.                                  */
+int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t *pi, const double *V_pi, float *w,
+                     double *grad, double *objective, double tol, int64_t max_iter,
+                     void *hip_stream, mdpvi_stats *st, int64_t *iterations);
+
+/* Autotuner: times every applicable sweep form (direct, and LDS slabs of
+ * 1..K-1 low digits that fit 64 KB) on this instance, `trials` single sweeps
+ * each from V (device float[N], read only; the sweeps write the handle's
+ * scratch), keeps the form with the smallest median time, and records it
+ * for the shape (GPU arch, K, C, J, sizes): later vi_solve calls in automatic
+ * mode on any handle of that shape use it.  When the environment variable
+ * MDPVI_AUTOTUNE_CACHE names a file, the records are loaded from and saved
+ * to it as JSON.  best_form / best_us (host, nullable): the chosen form and
+ * its median microseconds per sweep.  Synchronous.
+ * Errors: MDPVI_EINVAL, MDPVI_EDEVICE, MDPVI_ENOMEM.                        */
+int mdp_autotune(mdpvi_mdp_t h, const float *V, int32_t trials, void *hip_stream,
+                 int32_t *best_form, double *best_us);
+
 /* Per-sweep kernel timing for the iterative calls of this handle: when on,
  * every sweep launch is bracketed by two HIP events and their elapsed times
  * are summed into mdpvi_stats.sweep_seconds (a measurement aid; it adds two

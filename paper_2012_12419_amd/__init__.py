@@ -80,7 +80,18 @@ SIGNATURES = {
     "batch_offsets": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int64)]),
     "vi_solve_batch": (ctypes.c_int, [_vp, _vp, _c_double, _c_int64, _vp, ctypes.POINTER(Stats),
                                       ctypes.POINTER(_c_int64), ctypes.POINTER(_c_double)]),
+    "policy_extract_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "policy_extract_batch_f64": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "policy_greedy_batch": (ctypes.c_int, [_vp, _c_int32, _vp, _vp]),
+    "policy_eval_batch": (ctypes.c_int, [_vp, _vp, _vp, _c_double, _c_int64, _vp, ctypes.POINTER(Stats),
+                                         ctypes.POINTER(_c_int64), ctypes.POINTER(_c_double)]),
+    "vi_adjoint_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_c_double),
+                                        ctypes.POINTER(_c_double), _c_double, _c_int64, _vp,
+                                        ctypes.POINTER(Stats), ctypes.POINTER(_c_int64)]),
     "mdp_set_timing": (ctypes.c_int, [_vp, _c_int32]),
+    "mdp_set_sweep_form": (ctypes.c_int, [_vp, _c_int32]),
+    "mdp_autotune": (ctypes.c_int, [_vp, _vp, _c_int32, _vp, ctypes.POINTER(_c_int32),
+                                    ctypes.POINTER(_c_double)]),
     "mdpvi_last_error": (ctypes.c_char_p, []),
 }
 
@@ -188,6 +199,21 @@ class MDP:
     def set_timing(self, on: bool = True):
         """Bracket every sweep with HIP events (stats['sweep_seconds'])."""
         _check(load().mdp_set_timing(self._h, 1 if on else 0))
+
+    def set_sweep_form(self, slab_digits: int = -1):
+        """-1 automatic, 0 direct, t > 0 LDS slab of t low digits."""
+        _check(load().mdp_set_sweep_form(self._h, int(slab_digits)))
+
+    def autotune(self, V=None, trials: int = 10, stream=None):
+        """Time every sweep form on this instance; returns (best form, us per sweep)."""
+        import torch
+        if V is None:
+            V = torch.zeros(self.num_states, dtype=torch.float32, device="cuda")
+        f = _c_int32()
+        us = _c_double()
+        _check(load().mdp_autotune(self._h, _dev_tensor(V, torch.float32, self.num_states, "V"),
+                                   int(trials), _stream_ptr(stream), ctypes.byref(f), ctypes.byref(us)))
+        return f.value, us.value
 
     # --------------------------------------------------------------- calls
     def vi_solve(self, V, tol: float = 1e-6, max_iter: int = 1_000_000, stream=None) -> dict:
@@ -305,3 +331,65 @@ class Batch:
                                      float(tol), int(max_iter), _stream_ptr(stream), ctypes.byref(st),
                                      its, res), st)
         return st.as_dict(), list(its), list(res)
+
+    def policy_extract(self, V, pi=None, gap=None, want_gap: bool = True, stream=None):
+        import torch
+        n = self.num_states
+        if pi is None:
+            pi = torch.empty(n, dtype=torch.uint8, device=V.device)
+        if gap is None and want_gap:
+            gap = torch.empty(n, dtype=torch.float32, device=V.device)
+        p = _dev_tensor(pi, torch.uint8, n, "pi")
+        g = _dev_tensor(gap, torch.float32, n, "gap") if gap is not None else None
+        if V.dtype == torch.float64:
+            _check(load().policy_extract_batch_f64(self._h, _dev_tensor(V, torch.float64, n, "V"), p, g,
+                                                   _stream_ptr(stream)))
+        else:
+            _check(load().policy_extract_batch(self._h, _dev_tensor(V, torch.float32, n, "V"), p, g,
+                                               _stream_ptr(stream)))
+        return pi, gap
+
+    def policy_greedy(self, kind: str = "least_loaded", pi=None, stream=None):
+        import torch
+        if pi is None:
+            pi = torch.empty(self.num_states, dtype=torch.uint8, device="cuda")
+        _check(load().policy_greedy_batch(self._h, {"least_loaded": 0, "first_fit": 1}[kind],
+                                          _dev_tensor(pi, torch.uint8, self.num_states, "pi"),
+                                          _stream_ptr(stream)))
+        return pi
+
+    def policy_eval(self, pi, V=None, tol: float = 1e-12, max_iter: int = 10_000_000, stream=None):
+        """Returns (V, stats, iterations[n], residuals[n])."""
+        import torch
+        n = self.num_states
+        if V is None:
+            V = torch.zeros(n, dtype=torch.float64, device=pi.device)
+        st = Stats()
+        its = (_c_int64 * self.n)()
+        res = (_c_double * self.n)()
+        _check(load().policy_eval_batch(self._h, _dev_tensor(pi, torch.uint8, n, "pi"),
+                                        _dev_tensor(V, torch.float64, n, "V"), float(tol), int(max_iter),
+                                        _stream_ptr(stream), ctypes.byref(st), its, res), st)
+        return V, st.as_dict(), list(its), list(res)
+
+    def vi_adjoint(self, pi, V_pi, J_sizes, w=None, tol: float = 1e-10, max_iter: int = 10_000_000,
+                   stream=None):
+        """Returns (list of per-instance gradients, objectives[n], w, stats, iterations[n])."""
+        import torch
+        n = self.num_states
+        if w is None:
+            w = torch.zeros(n, dtype=torch.float32, device=pi.device)
+        total = sum(2 * J + 2 for J in J_sizes)
+        g = (_c_double * total)()
+        obj = (_c_double * self.n)()
+        its = (_c_int64 * self.n)()
+        st = Stats()
+        _check(load().vi_adjoint_batch(self._h, _dev_tensor(pi, torch.uint8, n, "pi"),
+                                       _dev_tensor(V_pi, torch.float64, n, "V_pi"),
+                                       _dev_tensor(w, torch.float32, n, "w"), g, obj, float(tol),
+                                       int(max_iter), _stream_ptr(stream), ctypes.byref(st), its), st)
+        out, at = [], 0
+        for J in J_sizes:
+            out.append(list(g[at:at + 2 * J + 2]))
+            at += 2 * J + 2
+        return out, list(obj), w, st.as_dict(), list(its)

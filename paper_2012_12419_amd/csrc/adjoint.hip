@@ -21,75 +21,13 @@
 // All weights are non-negative: w is FP32, sums are FP64, one rounding per
 // state, and the residual is the 1-norm ||w' - w||_1 (the norm in which
 // P_pi^T is a contraction).
+#include "adjoint_impl.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 
 #include <type_traits>
 
 namespace mdpvi {
-
-template <int KMAX, int JMAX, typename Idx>
-__device__ __forceinline__ double adjoint_occupancy(const Model& M, const uint8_t* __restrict__ pi,
-                                                    const float* __restrict__ win,
-                                                    float* __restrict__ wout, Idx o) {
-  const Idx nocc = static_cast<Idx>(M.n_occ);
-  int n[KMAX];
-  decode<KMAX>(M, o, n);
-  int load = 0;
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) load += n[k];
-
-  // arrival inflow into occupancy n'
-  double B = 0.0;
-#pragma unroll
-  for (int e = 0; e < JMAX; ++e) {
-    if (e < M.J) {
-      const Idx s = o + e * nocc;
-      if (pi[s] == M.K) B += static_cast<double>(win[s]);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    if (k < M.K) {
-      const Idx st = static_cast<Idx>(M.stride[k]);
-#pragma unroll
-      for (int e = 0; e < JMAX; ++e) {
-        if (e < M.J && n[k] >= M.size[e]) {
-          const Idx src = o - static_cast<Idx>(M.size[e]) * st + e * nocc;
-          if (pi[src] == k) B += static_cast<double>(win[src]);
-        }
-      }
-    }
-  }
-
-  const double idle = M.mu_L * static_cast<double>(M.KC - load);
-  double dsum = 0.0;
-#pragma unroll
-  for (int e = 0; e < JMAX; ++e) {
-    if (e < M.J) {
-      const Idx base = o + e * nocc;
-      const float wold = win[base];
-      double acc = fma(M.p[e], B, idle * static_cast<double>(wold));
-      double rs = 0.0;
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        if (k < M.K) {
-          const Idx st = static_cast<Idx>(M.stride[k]);
-          if (n[k] < M.C) acc = fma(M.mu_L * (n[k] + 1), static_cast<double>(win[base + st]), acc);
-          if (n[k] == 0) {
-            for (int x = 0; x <= M.C; ++x) rs += static_cast<double>(win[base + static_cast<Idx>(x) * st]);
-          }
-        }
-      }
-      acc = fma(M.nu_L, rs, acc);
-      const double c = (o == 0) ? M.c_obj[e] : 0.0;
-      const float wn = static_cast<float>(fma(M.gamma, acc, c));
-      wout[base] = wn;
-      dsum += fabs(static_cast<double>(wn) - static_cast<double>(wold));
-    }
-  }
-  return dsum;
-}
 
 template <int KMAX, int JMAX, typename Idx>
 __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(Model M, const uint8_t* __restrict__ pi,
@@ -130,70 +68,11 @@ __global__ __launch_bounds__(kBlock) void grad_partial_kernel(Model M, const uin
   double g[TMAX];
 #pragma unroll
   for (int t = 0; t < TMAX; ++t) g[t] = 0.0;
-  const Idx nocc = static_cast<Idx>(M.n_occ);
-  const double Lam = M.Lam, L2 = M.Lam * M.Lam, lt = M.lam_tot;
   const Idx base0 = static_cast<Idx>(blockIdx.x) * (kBlock * kOccPerThread) + threadIdx.x;
   for (int i = 0; i < kOccPerThread; ++i) {
     const Idx o = base0 + static_cast<Idx>(i * kBlock);
-    if (o >= nocc) break;
-    int n[KMAX];
-    decode<KMAX>(M, o, n);
-#pragma unroll
-    for (int e = 0; e < JMAX; ++e) {
-      if (e < M.J) {
-        const Idx s = o + e * nocc;
-        const double ws = static_cast<double>(w[s]);
-        const int a = pi[s];
-        Idx m = o;
-        double R = -M.cost[e];
-        if (a < M.K) {
-          Idx st = 0;
-#pragma unroll
-          for (int k = 0; k < KMAX; ++k)
-            if (k == a) st = static_cast<Idx>(M.stride[k]);
-          m = o + static_cast<Idx>(M.size[e]) * st;
-          R = M.reward[e];
-        }
-        const double Vs = V[s];
-        double darr[JMAX];
-        double G = 0.0;
-#pragma unroll
-        for (int jj = 0; jj < JMAX; ++jj) {
-          darr[jj] = 0.0;
-          if (jj < M.J) {
-            darr[jj] = V[m + jj * nocc] - Vs;
-            G = fma(M.lam[jj], darr[jj], G);
-          }
-        }
-        double sdep = 0.0, sres = 0.0;
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-          if (k < M.K) {
-            const Idx st = static_cast<Idx>(M.stride[k]);
-            if (n[k] > 0) sdep = fma(static_cast<double>(n[k]), V[s - st] - Vs, sdep);
-            sres += V[s - static_cast<Idx>(n[k]) * st] - Vs;
-          }
-        }
-        G = fma(M.mu, sdep, fma(M.nu, sres, G));
-        const double gw = M.gamma * ws;
-#pragma unroll
-        for (int jj = 0; jj < JMAX; ++jj) {
-          if (jj < M.J) {
-            const double dP = darr[jj] / Lam - G / L2;
-            const double dr = R * (Lam - lt) / L2;
-            g[jj] = fma(ws, dr, fma(gw, dP, g[jj]));
-          }
-        }
-        const double KC = static_cast<double>(M.KC), K = static_cast<double>(M.K);
-        g[JMAX] = fma(ws, -lt * R * KC / L2, fma(gw, sdep / Lam - KC * G / L2, g[JMAX]));
-        g[JMAX + 1] = fma(ws, -lt * R * K / L2, fma(gw, sres / Lam - K * G / L2, g[JMAX + 1]));
-        if (a < M.K) {
-#pragma unroll
-          for (int jj = 0; jj < JMAX; ++jj)
-            if (jj == e) g[JMAX + 2 + jj] = fma(ws, lt / Lam, g[JMAX + 2 + jj]);
-        }
-      }
-    }
+    if (o >= static_cast<Idx>(M.n_occ)) break;
+    grad_occupancy<KMAX, JMAX>(M, pi, V, w, o, g);
   }
   // workgroup reduction in a fixed order: wavefront shuffles, then the
   // wavefront partials summed by thread t for entry t

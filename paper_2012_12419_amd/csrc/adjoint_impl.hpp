@@ -1,0 +1,142 @@
+// adjoint_impl.hpp -- per-occupancy device functions of the transposed
+// (adjoint) sweep and of the gradient accumulation, shared by the
+// single-instance kernels and the batched forms.
+#pragma once
+
+#include "device.hpp"
+
+namespace mdpvi {
+
+template <int KMAX, int JMAX, typename Idx>
+__device__ __forceinline__ double adjoint_occupancy(const Model& M, const uint8_t* __restrict__ pi,
+                                                    const float* __restrict__ win,
+                                                    float* __restrict__ wout, Idx o) {
+  const Idx nocc = static_cast<Idx>(M.n_occ);
+  int n[KMAX];
+  decode<KMAX>(M, o, n);
+  int load = 0;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) load += n[k];
+
+  // arrival inflow into occupancy n'
+  double B = 0.0;
+#pragma unroll
+  for (int e = 0; e < JMAX; ++e) {
+    if (e < M.J) {
+      const Idx s = o + e * nocc;
+      if (pi[s] == M.K) B += static_cast<double>(win[s]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k < M.K) {
+      const Idx st = static_cast<Idx>(M.stride[k]);
+#pragma unroll
+      for (int e = 0; e < JMAX; ++e) {
+        if (e < M.J && n[k] >= M.size[e]) {
+          const Idx src = o - static_cast<Idx>(M.size[e]) * st + e * nocc;
+          if (pi[src] == k) B += static_cast<double>(win[src]);
+        }
+      }
+    }
+  }
+
+  const double idle = M.mu_L * static_cast<double>(M.KC - load);
+  double dsum = 0.0;
+#pragma unroll
+  for (int e = 0; e < JMAX; ++e) {
+    if (e < M.J) {
+      const Idx base = o + e * nocc;
+      const float wold = win[base];
+      double acc = fma(M.p[e], B, idle * static_cast<double>(wold));
+      double rs = 0.0;
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < M.K) {
+          const Idx st = static_cast<Idx>(M.stride[k]);
+          if (n[k] < M.C) acc = fma(M.mu_L * (n[k] + 1), static_cast<double>(win[base + st]), acc);
+          if (n[k] == 0) {
+            for (int x = 0; x <= M.C; ++x) rs += static_cast<double>(win[base + static_cast<Idx>(x) * st]);
+          }
+        }
+      }
+      acc = fma(M.nu_L, rs, acc);
+      const double c = (o == 0) ? M.c_obj[e] : 0.0;
+      const float wn = static_cast<float>(fma(M.gamma, acc, c));
+      wout[base] = wn;
+      dsum += fabs(static_cast<double>(wn) - static_cast<double>(wold));
+    }
+  }
+  return dsum;
+}
+
+// Adds the gradient terms of the classes of occupancy o to g[] (layout:
+// lambda at 0..JMAX-1, mu at JMAX, nu at JMAX+1, r at JMAX+2..).
+template <int KMAX, int JMAX, typename Idx>
+__device__ __forceinline__ void grad_occupancy(const Model& M, const uint8_t* __restrict__ pi,
+                                               const double* __restrict__ V,
+                                               const float* __restrict__ w, Idx o,
+                                               double (&g)[2 * JMAX + 2]) {
+  const Idx nocc = static_cast<Idx>(M.n_occ);
+  const double Lam = M.Lam, L2 = M.Lam * M.Lam, lt = M.lam_tot;
+  int n[KMAX];
+  decode<KMAX>(M, o, n);
+#pragma unroll
+  for (int e = 0; e < JMAX; ++e) {
+    if (e < M.J) {
+      const Idx s = o + e * nocc;
+      const double ws = static_cast<double>(w[s]);
+      const int a = pi[s];
+      Idx m = o;
+      double R = -M.cost[e];
+      if (a < M.K) {
+        Idx st = 0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k == a) st = static_cast<Idx>(M.stride[k]);
+        m = o + static_cast<Idx>(M.size[e]) * st;
+        R = M.reward[e];
+      }
+      const double Vs = V[s];
+      double darr[JMAX];
+      double G = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < JMAX; ++jj) {
+        darr[jj] = 0.0;
+        if (jj < M.J) {
+          darr[jj] = V[m + jj * nocc] - Vs;
+          G = fma(M.lam[jj], darr[jj], G);
+        }
+      }
+      double sdep = 0.0, sres = 0.0;
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < M.K) {
+          const Idx st = static_cast<Idx>(M.stride[k]);
+          if (n[k] > 0) sdep = fma(static_cast<double>(n[k]), V[s - st] - Vs, sdep);
+          sres += V[s - static_cast<Idx>(n[k]) * st] - Vs;
+        }
+      }
+      G = fma(M.mu, sdep, fma(M.nu, sres, G));
+      const double gw = M.gamma * ws;
+#pragma unroll
+      for (int jj = 0; jj < JMAX; ++jj) {
+        if (jj < M.J) {
+          const double dP = darr[jj] / Lam - G / L2;
+          const double dr = R * (Lam - lt) / L2;
+          g[jj] = fma(ws, dr, fma(gw, dP, g[jj]));
+        }
+      }
+      const double KC = static_cast<double>(M.KC), K = static_cast<double>(M.K);
+      g[JMAX] = fma(ws, -lt * R * KC / L2, fma(gw, sdep / Lam - KC * G / L2, g[JMAX]));
+      g[JMAX + 1] = fma(ws, -lt * R * K / L2, fma(gw, sres / Lam - K * G / L2, g[JMAX + 1]));
+      if (a < M.K) {
+#pragma unroll
+        for (int jj = 0; jj < JMAX; ++jj)
+          if (jj == e) g[JMAX + 2 + jj] = fma(ws, lt / Lam, g[JMAX + 2 + jj]);
+      }
+    }
+  }
+}
+
+}  // namespace mdpvi

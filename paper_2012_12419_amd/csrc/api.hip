@@ -12,7 +12,12 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -36,6 +41,7 @@ struct mdpvi_mdp {
   size_t aux_bytes = 0;
   double* out_host = nullptr;   // pinned, 2 * kMaxJ + 3 doubles
   bool timing = false;          // bracket every sweep with events
+  int slab_t = -1;              // sweep form: -1 automatic, 0 direct, t > 0 slab of t digits
   hipEvent_t* sweep_ev = nullptr;   // 2 * kMaxChunk events (created on demand)
 };
 
@@ -226,6 +232,77 @@ int run_loop(mdpvi_mdp* h, T* buf0, double tol, int64_t max_iter, hipStream_t s,
   return MDPVI_OK;
 }
 
+// ---------------------------------------------------------------- tuning cache
+//
+// Best sweep form per problem shape, kept in memory and, when the
+// environment variable MDPVI_AUTOTUNE_CACHE names a file, in that JSON file:
+//   {"gfx950|K=6|C=10|J=3|S=1,2,3": [3, 9.81], ...}   (form, microseconds per sweep)
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, double>> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const Model& M) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+  }
+  std::ostringstream k;
+  k << arch << "|K=" << M.K << "|C=" << M.C << "|J=" << M.J << "|S=";
+  for (int j = 0; j < M.J; ++j) k << (j ? "," : "") << M.size[j];
+  return k.str();
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("MDPVI_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ifstream f(path);
+  if (!f) return;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  // entries of the form "key": [form, us]
+  size_t pos = 0;
+  while ((pos = s.find('"', pos)) != std::string::npos) {
+    const size_t end = s.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    const std::string key = s.substr(pos + 1, end - pos - 1);
+    const size_t lb = s.find('[', end), rb = s.find(']', end);
+    if (lb == std::string::npos || rb == std::string::npos || lb > rb) break;
+    int form = 0;
+    double us = 0.0;
+    if (std::sscanf(s.c_str() + lb + 1, "%d , %lf", &form, &us) == 2) g_tune[key] = {form, us};
+    pos = rb + 1;
+  }
+}
+
+void tune_store_locked() {
+  const char* path = std::getenv("MDPVI_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ofstream f(path);
+  f << "{\n";
+  size_t i = 0;
+  for (const auto& kv : g_tune) {
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "[%d, %.4f]", kv.second.first, kv.second.second);
+    f << "  \"" << kv.first << "\": " << buf << (++i < g_tune.size() ? ",\n" : "\n");
+  }
+  f << "}\n";
+}
+
+// Cached form for M, or -2 when none is known.
+int tune_lookup(const Model& M) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(tune_key(M));
+  return it == g_tune.end() ? -2 : it->second.first;
+}
+
 // Fill a Model from validated parameters (shared by single and batched builds).
 int fill_model(const mdpvi_params* p, Model& M, int64_t& pairs_out) {
   if (!p) return fail(MDPVI_EINVAL, "NULL argument");
@@ -315,15 +392,26 @@ struct mdpvi_batch {
   std::vector<Model> models;
   std::vector<int64_t> offsets;      // n + 1 state offsets
   std::vector<int64_t> pairs;        // feasible pairs per sweep, per instance
-  std::vector<int32_t> lds_list, round_list;
-  std::vector<mdpvi::Tile> tiles;
-  int lds_maxK = 1, lds_maxJ = 1, rnd_maxK = 1, rnd_maxJ = 1;
+  std::vector<int32_t> lds_list, round_list, all_list;
+  std::vector<mdpvi::Tile> tiles;        // round-form instances (value iteration)
+  std::vector<mdpvi::Tile> tiles_all;    // every instance (other passes)
+  std::vector<int32_t> tile_begin;       // n+1 offsets of each instance in tiles_all
+  int lds_maxK = 1, lds_maxJ = 1, rnd_maxK = 1, rnd_maxJ = 1, maxK = 1, maxJ = 1;
   size_t lds_bytes = 0;
   int device = -1;
   mdpvi::BatchInst* d_inst = nullptr;
   int32_t* d_lds = nullptr;
   int32_t* d_round = nullptr;
   mdpvi::Tile* d_tiles = nullptr;
+  mdpvi::Tile* d_tiles_all = nullptr;
+  int32_t* d_all = nullptr;
+  int32_t* d_tile_begin = nullptr;
+  int* d_flags = nullptr;
+  int* h_flags = nullptr;           // pinned
+  double* d_gpart = nullptr;        // gradient partials per tile
+  double* d_gout = nullptr;         // n rows of 2*kMaxJ+3
+  double* h_gout = nullptr;         // pinned
+  void* W2 = nullptr;               // FP64 ping-pong partner (evaluation), on first use
   mdpvi::BatchCtl* d_ctl = nullptr;
   int* d_remaining = nullptr;
   mdpvi::BatchOut* d_out = nullptr;
@@ -376,6 +464,72 @@ int mdp_set_timing(mdpvi_mdp_t h, int32_t per_sweep_events) {
   return MDPVI_OK;
 }
 
+int mdp_set_sweep_form(mdpvi_mdp_t h, int32_t slab_digits) {
+  if (!h) return fail(MDPVI_EINVAL, "NULL handle");
+  if (slab_digits < -1 || slab_digits >= h->M.K)
+    return fail(MDPVI_EINVAL, "slab_digits=%d outside [-1, K-1=%d]", slab_digits, h->M.K - 1);
+  if (slab_digits > 0) {
+    uint64_t occ = 1;
+    for (int k = 0; k < slab_digits; ++k) occ *= static_cast<uint64_t>(h->M.R);
+    if (occ * (8 + 4 * static_cast<uint64_t>(h->M.J)) > 64 * 1024 || !mdpvi::use_32bit_index(h->M))
+      return fail(MDPVI_EINVAL, "a slab of %d digits does not fit the LDS budget", slab_digits);
+  }
+  h->slab_t = slab_digits;
+  return MDPVI_OK;
+}
+
+int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream,
+                 int32_t* best_form, double* best_us) {
+  if (!h || !V) return fail(MDPVI_EINVAL, "NULL handle or value array");
+  if (trials < 1) return fail(MDPVI_EINVAL, "trials=%d must be >= 1", trials);
+  int rc = ensure_scratch(h, static_cast<size_t>(h->M.n_states) * sizeof(float));
+  if (rc) return rc;
+  const Model& M = h->M;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  std::vector<int> forms = {0};
+  if (mdpvi::use_32bit_index(M)) {
+    uint64_t occ = 1;
+    for (int t = 1; t < M.K; ++t) {
+      occ *= static_cast<uint64_t>(M.R);
+      if (occ * (8 + 4 * static_cast<uint64_t>(M.J)) <= 64 * 1024 &&
+          static_cast<uint64_t>(M.n_occ) / occ >= 64)
+        forms.push_back(t);
+    }
+  }
+  float* out = static_cast<float*>(h->vbuf);
+  int best = 0;
+  double best_t = 1e300;
+  for (int form : forms) {
+    // sweep 0 (no stopping test) from V into the scratch buffer, untimed once
+    HIP_TRY(mdpvi::launch_ctl_init(h->ctl, s));
+    HIP_TRY(mdpvi::launch_vi_sweep(M, V, out, h->ctl, 0, 1.0, s, form));
+    std::vector<float> ms(trials);
+    for (int r = 0; r < trials; ++r) {
+      HIP_TRY(mdpvi::launch_ctl_init(h->ctl, s));
+      HIP_TRY(hipEventRecord(h->ev0, s));
+      HIP_TRY(mdpvi::launch_vi_sweep(M, V, out, h->ctl, 0, 1.0, s, form));
+      HIP_TRY(hipEventRecord(h->ev1, s));
+      HIP_TRY(hipEventSynchronize(h->ev1));
+      HIP_TRY(hipEventElapsedTime(&ms[r], h->ev0, h->ev1));
+    }
+    std::sort(ms.begin(), ms.end());
+    const double med = ms[trials / 2] * 1e3;
+    if (med < best_t) {
+      best_t = med;
+      best = form;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune[tune_key(M)] = {best, best_t};
+    tune_store_locked();
+  }
+  if (best_form) *best_form = best;
+  if (best_us) *best_us = best_t;
+  return MDPVI_OK;
+}
+
 int64_t mdp_num_states(mdpvi_mdp_t h) { return h ? h->M.n_states : -1; }
 int32_t mdp_num_actions(mdpvi_mdp_t h) { return h ? h->M.K + 1 : -1; }
 int64_t mdp_feasible_pairs(mdpvi_mdp_t h) { return h ? h->feasible_pairs : -1; }
@@ -389,10 +543,15 @@ int vi_solve(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, void* hip_st
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const Model& M = h->M;
+  int slab_t = h->slab_t;
+  if (slab_t < 0) {
+    const int cached = tune_lookup(M);
+    slab_t = cached >= 0 ? cached : mdpvi::slab_digits(M);
+  }
   return run_loop<float>(h, V, tol, max_iter, s, st, 8.0 * M.n_states,
                          static_cast<double>(h->feasible_pairs),
                          [&](long long j, float* in, float* out) {
-                           return mdpvi::launch_vi_sweep(M, in, out, h->ctl, j, tol, s);
+                           return mdpvi::launch_vi_sweep(M, in, out, h->ctl, j, tol, s, slab_t);
                          });
 }
 
@@ -510,7 +669,8 @@ int ensure_batch_device(mdpvi_batch* b) {
     inst[i].ctl = -1;
   }
   for (int32_t i : b->lds_list) inst[i].lds = 1;
-  for (int32_t i : b->round_list) inst[i].ctl = n_ctl++;
+  for (int i = 0; i < n; ++i) inst[i].ctl = i;
+  n_ctl = n;
   auto dalloc = [&](void** p, size_t bytes) -> int {
     if (bytes == 0) bytes = 16;
     if (hipMalloc(p, bytes) != hipSuccess) {
@@ -524,12 +684,24 @@ int ensure_batch_device(mdpvi_batch* b) {
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_lds), b->lds_list.size() * sizeof(int32_t)))) return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_round), b->round_list.size() * sizeof(int32_t)))) return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_tiles), b->tiles.size() * sizeof(mdpvi::Tile)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_tiles_all), b->tiles_all.size() * sizeof(mdpvi::Tile)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_all), n * sizeof(int32_t)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_tile_begin), (n + 1) * sizeof(int32_t)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_flags), n * sizeof(int)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_gpart),
+                   mdpvi::batch_grad_partial_doubles(static_cast<int>(b->tiles_all.size()), b->maxJ) * sizeof(double))))
+    return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_gout), static_cast<size_t>(n) * (2 * MDPVI_MAX_J + 3) * sizeof(double))))
+    return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_ctl), std::max(n_ctl, 1) * sizeof(mdpvi::BatchCtl)))) return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_remaining), sizeof(int)))) return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_out), n * sizeof(mdpvi::BatchOut)))) return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->W), std::max<int64_t>(b->offsets[n], 1) * sizeof(float)))) return rc;
   if (hipHostMalloc(reinterpret_cast<void**>(&b->h_remaining), sizeof(int), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&b->h_out), n * sizeof(mdpvi::BatchOut), hipHostMallocDefault) != hipSuccess)
+      hipHostMalloc(reinterpret_cast<void**>(&b->h_out), n * sizeof(mdpvi::BatchOut), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&b->h_flags), n * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&b->h_gout), static_cast<size_t>(n) * (2 * MDPVI_MAX_J + 3) * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess)
     return fail(MDPVI_ENOMEM, "hipHostMalloc of batch outputs failed");
   HIP_TRY(hipMemcpy(b->d_inst, inst.data(), n * sizeof(mdpvi::BatchInst), hipMemcpyHostToDevice));
   if (!b->lds_list.empty())
@@ -538,6 +710,10 @@ int ensure_batch_device(mdpvi_batch* b) {
     HIP_TRY(hipMemcpy(b->d_round, b->round_list.data(), b->round_list.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   if (!b->tiles.empty())
     HIP_TRY(hipMemcpy(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(mdpvi::Tile), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_tiles_all, b->tiles_all.data(), b->tiles_all.size() * sizeof(mdpvi::Tile),
+                    hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_all, b->all_list.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_tile_begin, b->tile_begin.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
@@ -601,6 +777,16 @@ int mdp_build_batch(const mdpvi_params* p, int32_t n, mdpvi_batch_t* out) {
       for (uint32_t t = 0; t < static_cast<uint32_t>(M.n_occ); t += per) b->tiles.push_back({i, t});
     }
   }
+  b->tile_begin.push_back(0);
+  for (int i = 0; i < n; ++i) {
+    const Model& M = b->models[i];
+    b->all_list.push_back(i);
+    b->maxK = std::max(b->maxK, M.K);
+    b->maxJ = std::max(b->maxJ, M.J);
+    const uint32_t per = mdpvi::kBlock * mdpvi::kOccPerThread;
+    for (uint32_t t = 0; t < static_cast<uint32_t>(M.n_occ); t += per) b->tiles_all.push_back({i, t});
+    b->tile_begin.push_back(static_cast<int32_t>(b->tiles_all.size()));
+  }
   std::sort(cost.begin(), cost.end(), [](auto& x, auto& y) { return x.first > y.first; });
   for (auto& c : cost) b->lds_list.push_back(c.second);
   b->lds_bytes = static_cast<size_t>(2 * max_lds_n) * sizeof(float);
@@ -615,6 +801,15 @@ void mdp_free_batch(mdpvi_batch_t b) {
   (void)hipFree(b->d_lds);
   (void)hipFree(b->d_round);
   (void)hipFree(b->d_tiles);
+  (void)hipFree(b->d_tiles_all);
+  (void)hipFree(b->d_all);
+  (void)hipFree(b->d_tile_begin);
+  (void)hipFree(b->d_flags);
+  (void)hipFree(b->d_gpart);
+  (void)hipFree(b->d_gout);
+  (void)hipFree(b->W2);
+  if (b->h_flags) (void)hipHostFree(b->h_flags);
+  if (b->h_gout) (void)hipHostFree(b->h_gout);
   (void)hipFree(b->d_ctl);
   (void)hipFree(b->d_remaining);
   (void)hipFree(b->d_out);
@@ -658,7 +853,7 @@ int vi_solve_batch(mdpvi_batch_t b, float* V, double tol, int64_t max_iter, void
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int n_round = static_cast<int>(b->round_list.size());
   const int n_lds = static_cast<int>(b->lds_list.size());
-  HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, n_round, b->d_remaining, s));
+  HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_round, n_round, b->d_remaining, b->d_flags, 0, s));
   HIP_TRY(hipEventRecord(b->ev0, s));
   HIP_TRY(hipEventRecord(b->ev_fork, s));
   HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
@@ -717,6 +912,187 @@ int vi_solve_batch(mdpvi_batch_t b, float* V, double tol, int64_t max_iter, void
   if (not_conv)
     return fail(MDPVI_ENOCONV, "%lld instances did not meet tol within max_iter", (long long)not_conv);
   return MDPVI_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batch passes
+
+namespace {
+
+// Flags every instance whose policy has an infeasible action; returns the
+// first such instance or -1.
+int batch_check_policy(mdpvi_batch* b, const uint8_t* pi, hipStream_t s, int* bad_inst) {
+  *bad_inst = -1;
+  HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_all, 0, b->d_remaining, b->d_flags, b->n, s));
+  HIP_TRY(mdpvi::launch_batch_check(b->d_inst, b->d_tiles_all, static_cast<int>(b->tiles_all.size()), b->maxK,
+                                    b->maxJ, pi, b->d_flags, s));
+  HIP_TRY(hipMemcpyAsync(b->h_flags, b->d_flags, b->n * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < b->n; ++i)
+    if (b->h_flags[i]) {
+      *bad_inst = i;
+      break;
+    }
+  return MDPVI_OK;
+}
+
+// Round-form loop over every instance: `round(j)` enqueues round j, `finish(issued)`
+// writes back odd finals and the per-instance outputs.  Fills stats from them.
+template <typename Round, typename Finish>
+int batch_all_rounds(mdpvi_batch* b, double tol, int64_t max_iter, hipStream_t s, mdpvi_stats* st,
+                     int64_t* iterations, double* residuals, double bytes_per_state, Round round,
+                     Finish finish) {
+  HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_all, b->n, b->d_remaining, b->d_flags, 0, s));
+  HIP_TRY(hipEventRecord(b->ev0, s));
+  int64_t issued = 0, chunk = 8;
+  while (issued < max_iter) {
+    const int64_t m = std::min<int64_t>(chunk, max_iter - issued);
+    for (int64_t k = 0; k < m; ++k) HIP_TRY(round(issued + k));
+    issued += m;
+    HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (*b->h_remaining <= 0) break;
+    if (chunk < kMaxChunk) chunk *= 2;
+  }
+  HIP_TRY(finish(issued));
+  HIP_TRY(hipMemcpyAsync(b->h_out, b->d_out, b->n * sizeof(mdpvi::BatchOut), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(b->ev1, s));
+  HIP_TRY(hipEventSynchronize(b->ev1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  int64_t max_it = 0, not_conv = 0, nan = 0;
+  double backups = 0, bytes = 0, max_res = 0, bound = 0;
+  for (int i = 0; i < b->n; ++i) {
+    const mdpvi::BatchOut& o = b->h_out[i];
+    if (iterations) iterations[i] = o.iterations;
+    if (residuals) residuals[i] = o.residual;
+    max_it = std::max<int64_t>(max_it, o.iterations);
+    backups += static_cast<double>(b->models[i].n_states) * o.iterations;
+    bytes += bytes_per_state * b->models[i].n_states * o.iterations;
+    if (std::isnan(o.residual)) {
+      ++nan;
+    } else {
+      if (!(o.residual < tol)) ++not_conv;
+      max_res = std::max(max_res, o.residual);
+      bound = std::max(bound, b->models[i].gamma / (1.0 - b->models[i].gamma) * o.residual);
+    }
+  }
+  if (st) {
+    st->iterations = max_it;
+    st->residual_inf = max_res;
+    st->bound_inf = bound;
+    st->seconds = ms * 1e-3;
+    st->backups = backups;
+    st->bytes = bytes;
+    st->sweep_seconds = 0.0;
+  }
+  if (nan) return fail(MDPVI_ENAN, "%lld instances produced a non-finite residual", (long long)nan);
+  if (not_conv) return fail(MDPVI_ENOCONV, "%lld instances did not meet tol within max_iter", (long long)not_conv);
+  return MDPVI_OK;
+}
+
+int batch_args(mdpvi_batch* b, double tol, int64_t max_iter) {
+  if (!(tol > 0)) return fail(MDPVI_EINVAL, "tol=%g must be > 0", tol);
+  if (max_iter < 1) return fail(MDPVI_EINVAL, "max_iter=%lld must be >= 1", (long long)max_iter);
+  return ensure_batch_device(b);
+}
+
+}  // namespace
+
+extern "C" {
+
+int policy_extract_batch(mdpvi_batch_t b, const float* V, uint8_t* pi, float* gap, void* hip_stream) {
+  if (!b || !V || !pi) return fail(MDPVI_EINVAL, "NULL batch, value or policy array");
+  int rc = ensure_batch_device(b);
+  if (rc) return rc;
+  HIP_TRY(mdpvi::launch_batch_extract(b->d_inst, b->d_tiles_all, static_cast<int>(b->tiles_all.size()), b->maxK,
+                                      b->maxJ, V, false, pi, gap, static_cast<hipStream_t>(hip_stream)));
+  return MDPVI_OK;
+}
+
+int policy_extract_batch_f64(mdpvi_batch_t b, const double* V, uint8_t* pi, float* gap, void* hip_stream) {
+  if (!b || !V || !pi) return fail(MDPVI_EINVAL, "NULL batch, value or policy array");
+  int rc = ensure_batch_device(b);
+  if (rc) return rc;
+  HIP_TRY(mdpvi::launch_batch_extract(b->d_inst, b->d_tiles_all, static_cast<int>(b->tiles_all.size()), b->maxK,
+                                      b->maxJ, V, true, pi, gap, static_cast<hipStream_t>(hip_stream)));
+  return MDPVI_OK;
+}
+
+int policy_greedy_batch(mdpvi_batch_t b, int32_t kind, uint8_t* pi, void* hip_stream) {
+  if (!b || !pi) return fail(MDPVI_EINVAL, "NULL batch or policy array");
+  if (kind != 0 && kind != 1) return fail(MDPVI_EINVAL, "kind=%d must be 0 or 1", kind);
+  int rc = ensure_batch_device(b);
+  if (rc) return rc;
+  HIP_TRY(mdpvi::launch_batch_greedy(b->d_inst, b->d_tiles_all, static_cast<int>(b->tiles_all.size()), b->maxK,
+                                     b->maxJ, kind, pi, static_cast<hipStream_t>(hip_stream)));
+  return MDPVI_OK;
+}
+
+int policy_eval_batch(mdpvi_batch_t b, const uint8_t* pi, double* V, double tol, int64_t max_iter,
+                      void* hip_stream, mdpvi_stats* st, int64_t* iterations, double* residuals) {
+  if (!b || !pi || !V) return fail(MDPVI_EINVAL, "NULL batch, policy or value array");
+  int rc = batch_args(b, tol, max_iter);
+  if (rc) return rc;
+  if (!b->W2) {
+    if (hipMalloc(&b->W2, std::max<int64_t>(b->offsets[b->n], 1) * sizeof(double)) != hipSuccess) {
+      b->W2 = nullptr;
+      return fail(MDPVI_ENOMEM, "hipMalloc of the FP64 batch scratch failed");
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int bad = -1;
+  if ((rc = batch_check_policy(b, pi, s, &bad))) return rc;
+  if (bad >= 0) return fail(MDPVI_EINVAL, "instance %d: policy has an infeasible action", bad);
+  double* W = static_cast<double*>(b->W2);
+  const int nt = static_cast<int>(b->tiles_all.size());
+  return batch_all_rounds(
+      b, tol, max_iter, s, st, iterations, residuals, 17.0,
+      [&](long long j) {
+        return mdpvi::launch_batch_eval_round(b->d_inst, b->d_tiles_all, nt, b->maxK, b->maxJ, pi, V, W, b->d_ctl,
+                                              b->d_remaining, j, tol, s);
+      },
+      [&](int64_t issued) {
+        return mdpvi::launch_batch_eval_finish(b->d_inst, b->d_all, b->n, V, W, b->d_ctl, issued, b->d_out, s);
+      });
+}
+
+int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t* pi, const double* V_pi, float* w, double* grad,
+                     double* objective, double tol, int64_t max_iter, void* hip_stream, mdpvi_stats* st,
+                     int64_t* iterations) {
+  if (!b || !pi || !V_pi || !w || !grad) return fail(MDPVI_EINVAL, "NULL batch, policy, value, adjoint or gradient");
+  int rc = batch_args(b, tol, max_iter);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int bad = -1;
+  if ((rc = batch_check_policy(b, pi, s, &bad))) return rc;
+  if (bad >= 0) return fail(MDPVI_EINVAL, "instance %d: policy has an infeasible action", bad);
+  const int nt = static_cast<int>(b->tiles_all.size());
+  rc = batch_all_rounds(
+      b, tol, max_iter, s, st, iterations, nullptr, 9.0,
+      [&](long long j) {
+        return mdpvi::launch_batch_adjoint_round(b->d_inst, b->d_tiles_all, nt, b->maxK, b->maxJ, pi, w, b->W,
+                                                 b->d_ctl, b->d_remaining, j, tol, s);
+      },
+      [&](int64_t issued) {
+        return mdpvi::launch_batch_adjoint_finish(b->d_inst, b->d_all, b->n, w, b->W, b->d_ctl, issued, b->d_out,
+                                                  s);
+      });
+  if (rc != MDPVI_OK && rc != MDPVI_ENOCONV) return rc;
+  HIP_TRY(mdpvi::launch_batch_grad(b->d_inst, b->d_tiles_all, nt, b->d_tile_begin, b->n, b->maxK, b->maxJ, pi, V_pi,
+                                   w, b->d_gpart, b->d_gout, s));
+  const size_t row = 2 * MDPVI_MAX_J + 3;
+  HIP_TRY(hipMemcpyAsync(b->h_gout, b->d_gout, b->n * row * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  size_t at = 0;
+  for (int i = 0; i < b->n; ++i) {
+    const int nth = 2 * b->models[i].J + 2;
+    std::memcpy(grad + at, b->h_gout + i * row, nth * sizeof(double));
+    at += nth;
+    if (objective) objective[i] = b->h_gout[i * row + nth];
+  }
+  return rc;
 }
 
 }  // extern "C"

@@ -19,9 +19,15 @@
 //   (the L2 caches of the 8 XCDs are not coherent with each other inside a
 //   kernel).  Rounds are enqueued in chunks; the host reads one counter of
 //   unfinished instances per chunk.
+//
+// Fixed-policy evaluation (FP64) and the adjoint sweeps of every instance run
+// in the round form; extraction, the greedy heuristic, the policy check and
+// the gradient pass are one kernel over the tiles of all instances.
 #include "batch.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
+#include "adjoint_impl.hpp"
+#include "policy_impl.hpp"
 #include "sweep_impl.hpp"
 
 #include <type_traits>
@@ -79,16 +85,53 @@ __global__ __launch_bounds__(kLdsBlock) void batch_lds_vi_kernel(const BatchInst
 
 // ---------------------------------------------------------------- round form
 
-// Per-instance control of the round form.
+// Sweep operations of the round form.
+struct VIOp {
+  using T = float;
+  static constexpr ResKind RK = ResKind::kMax;
+  template <int KM, int JM>
+  __device__ static double run(const Model& M, const uint8_t*, const T* in, T* out, uint32_t o) {
+    return backup_occupancy<KM, JM, uint32_t>(M, in, out, o);
+  }
+};
+struct EvalOp {
+  using T = double;
+  static constexpr ResKind RK = ResKind::kMax;
+  template <int KM, int JM>
+  __device__ static double run(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
+    return eval_occupancy<KM, JM, uint32_t>(M, pi, in, out, o);
+  }
+};
+struct AdjOp {
+  using T = float;
+  static constexpr ResKind RK = ResKind::kSum;
+  template <int KM, int JM>
+  __device__ static double run(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
+    return adjoint_occupancy<KM, JM, uint32_t>(M, pi, in, out, o);
+  }
+};
+
+// Per-instance control of the round form: true (for the whole workgroup) when
+// the instance already stopped.  The leader workgroup of the instance (its
+// first tile) records done_iter, counts the instance off and clears the
+// residual words of the next round.
+template <ResKind RK>
 __device__ __forceinline__ bool inst_stopped(BatchCtl* c, long long j, double tol, int* remaining,
                                              bool leader) {
   __shared__ int stop;
   if (threadIdx.x < kWave) {
     bool s = load_agent(&c->done_iter) >= 0;
     if (!s && j > 0) {
-      double v = __longlong_as_double(static_cast<long long>(
-          load_agent(&c->res[(j - 1) % kResSlots][threadIdx.x % kBatchLanes][0])));
-      v = wave_max(v);
+      double v = 0.0;
+      if (threadIdx.x < kBatchLanes)
+        v = __longlong_as_double(static_cast<long long>(
+            load_agent(&c->res[(j - 1) % kResSlots][threadIdx.x][0])));
+      if constexpr (RK == ResKind::kMax) {
+        v = wave_max(v);
+      } else {
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+      }
       if (!(v >= tol)) {
         s = true;
         if (leader && threadIdx.x == 0) {
@@ -105,56 +148,72 @@ __device__ __forceinline__ bool inst_stopped(BatchCtl* c, long long j, double to
   return false;
 }
 
-template <int KMAX, int JMAX>
+template <class Op, int KMAX, int JMAX>
 __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __restrict__ insts,
                                                               const Tile* __restrict__ tiles,
-                                                              float* __restrict__ V,
-                                                              float* __restrict__ W,
+                                                              typename Op::T* __restrict__ V,
+                                                              typename Op::T* __restrict__ W,
+                                                              const uint8_t* __restrict__ pi,
                                                               BatchCtl* __restrict__ ctl,
                                                               int* remaining, long long j, double tol) {
-  const Tile T = tiles[blockIdx.x];
-  const int i = T.inst;
-  const BatchInst& I = insts[i];
+  using T = typename Op::T;
+  const Tile tile = tiles[blockIdx.x];
+  const BatchInst& I = insts[tile.inst];
   const Model& M = I.M;
-  BatchCtl* c = ctl + I.ctl;
-  if (inst_stopped(c, j, tol, remaining, T.first != 0 ? false : true)) return;
-  const float* Vin = ((j & 1) ? W : V) + I.offset;
-  float* Vout = ((j & 1) ? V : W) + I.offset;
-  double dmax = 0.0;
+  BatchCtl* c = ctl + tile.inst;
+  if (inst_stopped<Op::RK>(c, j, tol, remaining, tile.first == 0)) return;
+  const T* Vin = ((j & 1) ? W : V) + I.offset;
+  T* Vout = ((j & 1) ? V : W) + I.offset;
+  const uint8_t* p = pi ? pi + I.offset : nullptr;
+  double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < kOccPerThread; ++k) {
-    const uint32_t o = T.first + threadIdx.x + k * kBlock;
+    const uint32_t o = tile.first + threadIdx.x + k * kBlock;
     if (o < static_cast<uint32_t>(M.n_occ)) {
-      const double d = backup_occupancy<KMAX, JMAX, uint32_t>(M, Vin, Vout, o);
-      dmax = (d > dmax || d != d) ? d : dmax;
+      const double d = Op::template run<KMAX, JMAX>(M, p, Vin, Vout, o);
+      if constexpr (Op::RK == ResKind::kMax) acc = (d > acc || d != d) ? d : acc;
+      else acc += d;
     }
   }
   __shared__ double part[kBlock / kWave];
-  dmax = wave_max(dmax);
-  if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = dmax;
+  if constexpr (Op::RK == ResKind::kMax) {
+    acc = wave_max(acc);
+  } else {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+  }
+  if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = part[0];
 #pragma unroll
-    for (int w = 1; w < kBlock / kWave; ++w) m = (part[w] > m || part[w] != part[w]) ? part[w] : m;
-    if (m != 0.0)
-      atomicMax(&c->res[j % kResSlots][(T.first / (kBlock * kOccPerThread)) % kBatchLanes][0],
-                static_cast<unsigned long long>(__double_as_longlong(m)));
+    for (int w = 1; w < kBlock / kWave; ++w) {
+      if constexpr (Op::RK == ResKind::kMax) m = (part[w] > m || part[w] != part[w]) ? part[w] : m;
+      else m += part[w];
+    }
+    unsigned long long* word = &c->res[j % kResSlots][(tile.first / (kBlock * kOccPerThread)) % kBatchLanes][0];
+    if (m != 0.0) {
+      if constexpr (Op::RK == ResKind::kMax)
+        atomicMax(word, static_cast<unsigned long long>(__double_as_longlong(m)));
+      else
+        atomicAdd(reinterpret_cast<double*>(word), m);
+    }
   }
 }
 
 // Copies the final iterate of instances that stopped after an odd number of
 // sweeps (it lives in W) back to V, and reports iterations and residuals.
+template <typename T, ResKind RK>
 __global__ void batch_round_finish_kernel(const BatchInst* __restrict__ insts,
                                           const int32_t* __restrict__ list, int n_list,
-                                          float* __restrict__ V, const float* __restrict__ W,
+                                          T* __restrict__ V, const T* __restrict__ W,
                                           BatchCtl* __restrict__ ctl, long long issued,
                                           BatchOut* __restrict__ out) {
   const int li = blockIdx.y;
   if (li >= n_list) return;
   const int i = list[li];
   const BatchInst& I = insts[i];
-  BatchCtl* c = ctl + I.ctl;
+  BatchCtl* c = ctl + i;
   const long long d = load_agent(&c->done_iter);
   const long long fin = d >= 0 ? d : issued;
   if (fin & 1) {
@@ -168,21 +227,155 @@ __global__ void batch_round_finish_kernel(const BatchInst* __restrict__ insts,
     for (int l = 0; l < kBatchLanes; ++l) {
       const double v =
           __longlong_as_double(static_cast<long long>(load_agent(&c->res[(fin - 1) % kResSlots][l][0])));
-      r = (v > r || v != v) ? v : r;
+      if constexpr (RK == ResKind::kMax) r = (v > r || v != v) ? v : r;
+      else r += v;
     }
     out[i].iterations = fin;
     out[i].residual = r;
   }
 }
 
-__global__ void batch_ctl_init_kernel(BatchCtl* ctl, int n, int* remaining) {
-  const int i = blockIdx.x;
-  if (i < n) {
-    if (threadIdx.x == 0) ctl[i].done_iter = -1;
+__global__ void batch_ctl_init_kernel(BatchCtl* ctl, const int32_t* __restrict__ list, int n_list,
+                                      int* remaining, int* flags, int n_flags) {
+  const int li = blockIdx.x;
+  if (li < n_list) {
+    BatchCtl* c = ctl + list[li];
+    if (threadIdx.x == 0) c->done_iter = -1;
     for (int w = threadIdx.x; w < kResSlots * kBatchLanes; w += blockDim.x)
-      ctl[i].res[w / kBatchLanes][w % kBatchLanes][0] = 0ull;
+      c->res[w / kBatchLanes][w % kBatchLanes][0] = 0ull;
   }
-  if (i == 0 && threadIdx.x == 0) *remaining = n;
+  if (li == 0) {
+    if (threadIdx.x == 0) *remaining = n_list;
+    for (int f = threadIdx.x; f < n_flags; f += blockDim.x) flags[f] = 0;
+  }
+}
+
+// ---------------------------------------------------------------- one-pass tile kernels
+
+template <int KMAX, int JMAX, typename T>
+__global__ __launch_bounds__(kBlock) void batch_extract_kernel(const BatchInst* __restrict__ insts,
+                                                                const Tile* __restrict__ tiles,
+                                                                const T* __restrict__ V,
+                                                                uint8_t* __restrict__ pi,
+                                                                float* __restrict__ gap) {
+  const Tile tile = tiles[blockIdx.x];
+  const BatchInst& I = insts[tile.inst];
+#pragma unroll
+  for (int k = 0; k < kOccPerThread; ++k) {
+    const uint32_t o = tile.first + threadIdx.x + k * kBlock;
+    if (o < static_cast<uint32_t>(I.M.n_occ))
+      extract_occupancy<KMAX, JMAX, T, uint32_t>(I.M, V + I.offset, pi + I.offset,
+                                                 gap ? gap + I.offset : nullptr, o);
+  }
+}
+
+template <int KMAX, int JMAX>
+__global__ __launch_bounds__(kBlock) void batch_greedy_kernel(const BatchInst* __restrict__ insts,
+                                                               const Tile* __restrict__ tiles, int kind,
+                                                               uint8_t* __restrict__ pi) {
+  const Tile tile = tiles[blockIdx.x];
+  const BatchInst& I = insts[tile.inst];
+#pragma unroll
+  for (int k = 0; k < kOccPerThread; ++k) {
+    const uint32_t o = tile.first + threadIdx.x + k * kBlock;
+    if (o < static_cast<uint32_t>(I.M.n_occ)) greedy_occupancy<KMAX, JMAX, uint32_t>(I.M, kind, pi + I.offset, o);
+  }
+}
+
+template <int KMAX, int JMAX>
+__global__ __launch_bounds__(kBlock) void batch_check_kernel(const BatchInst* __restrict__ insts,
+                                                              const Tile* __restrict__ tiles,
+                                                              const uint8_t* __restrict__ pi,
+                                                              int* __restrict__ flags) {
+  const Tile tile = tiles[blockIdx.x];
+  const BatchInst& I = insts[tile.inst];
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < kOccPerThread; ++k) {
+    const uint32_t o = tile.first + threadIdx.x + k * kBlock;
+    if (o < static_cast<uint32_t>(I.M.n_occ)) bad |= check_occupancy<KMAX, JMAX, uint32_t>(I.M, pi + I.offset, o);
+  }
+  if (bad) flags[tile.inst] = 1;
+}
+
+template <int KMAX, int JMAX>
+__global__ __launch_bounds__(kBlock) void batch_grad_partial_kernel(const BatchInst* __restrict__ insts,
+                                                                     const Tile* __restrict__ tiles,
+                                                                     const uint8_t* __restrict__ pi,
+                                                                     const double* __restrict__ V,
+                                                                     const float* __restrict__ w,
+                                                                     double* __restrict__ partial) {
+  constexpr int TMAX = 2 * JMAX + 2;
+  const Tile tile = tiles[blockIdx.x];
+  const BatchInst& I = insts[tile.inst];
+  double g[TMAX];
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t) g[t] = 0.0;
+  for (int k = 0; k < kOccPerThread; ++k) {
+    const uint32_t o = tile.first + threadIdx.x + k * kBlock;
+    if (o >= static_cast<uint32_t>(I.M.n_occ)) break;
+    grad_occupancy<KMAX, JMAX, uint32_t>(I.M, pi + I.offset, V + I.offset, w + I.offset, o, g);
+  }
+  __shared__ double part[kBlock / kWave][TMAX];
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t) {
+    double v = g[t];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if (lane == 0) part[wid][t] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < TMAX) {
+    double v = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kBlock / kWave; ++wv) v += part[wv][threadIdx.x];
+    partial[static_cast<size_t>(blockIdx.x) * TMAX + threadIdx.x] = v;
+  }
+}
+
+// One workgroup per instance: sums its tiles' partials in tile order and adds
+// the objective-weight terms; out rows hold 2*kMaxJ+3 doubles (gradient in
+// the packed order lambda_1..J, mu, nu, r_1..J, then J at index 2J+2).
+template <int JMAX>
+__global__ void batch_grad_final_kernel(const BatchInst* __restrict__ insts,
+                                        const int32_t* __restrict__ tile_begin,
+                                        const double* __restrict__ partial, const double* __restrict__ V,
+                                        double* __restrict__ out) {
+  constexpr int TMAX = 2 * JMAX + 2;
+  const int i = blockIdx.x;
+  const BatchInst& I = insts[i];
+  const Model& M = I.M;
+  const int t = threadIdx.x;
+  const size_t nocc = static_cast<size_t>(M.n_occ);
+  const double* Vi = V + I.offset;
+  double* o = out + static_cast<size_t>(i) * (2 * kMaxJ + 3);
+  if (t < TMAX) {
+    double v = 0.0;
+    for (int b = tile_begin[i]; b < tile_begin[i + 1]; ++b) v += partial[static_cast<size_t>(b) * TMAX + t];
+    int dst = -1;
+    if (t < JMAX) {
+      if (t < M.J) {
+        dst = t;
+        const double lt = M.lam_tot;
+        for (int e = 0; e < M.J; ++e)
+          v += ((e == t ? lt : 0.0) - M.lam[e]) / (lt * lt) * Vi[static_cast<size_t>(e) * nocc];
+      }
+    } else if (t == JMAX) {
+      dst = M.J;
+    } else if (t == JMAX + 1) {
+      dst = M.J + 1;
+    } else if (t - JMAX - 2 < M.J) {
+      dst = M.J + 2 + (t - JMAX - 2);
+    }
+    if (dst >= 0) o[dst] = v;
+  }
+  if (t == 0) {
+    double Jv = 0.0;
+    for (int e = 0; e < M.J; ++e) Jv = fma(M.c_obj[e], Vi[static_cast<size_t>(e) * nocc], Jv);
+    o[2 * M.J + 2] = Jv;
+  }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -219,30 +412,128 @@ hipError_t launch_batch_lds_vi(const BatchInst* insts, const int32_t* list, int 
   });
 }
 
-hipError_t launch_batch_ctl_init(BatchCtl* ctl, int n, int* remaining, hipStream_t s) {
-  hipLaunchKernelGGL(batch_ctl_init_kernel, dim3(n > 0 ? n : 1), dim3(64), 0, s, ctl, n, remaining);
+hipError_t launch_batch_ctl_init(BatchCtl* ctl, const int32_t* list, int n_list, int* remaining,
+                                 int* flags, int n_flags, hipStream_t s) {
+  hipLaunchKernelGGL(batch_ctl_init_kernel, dim3(n_list > 0 ? n_list : 1), dim3(64), 0, s, ctl, list,
+                     n_list, remaining, flags, n_flags);
   return hipGetLastError();
+}
+
+template <class Op>
+static hipError_t launch_round_t(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
+                                 int maxJ, typename Op::T* V, typename Op::T* W, const uint8_t* pi,
+                                 BatchCtl* ctl, int* remaining, long long j, double tol, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  return dispatch_kj_b(maxK, maxJ, [&](auto km, auto jm) {
+    constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
+    hipLaunchKernelGGL((batch_round_kernel<Op, KM, JM>), dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles,
+                       V, W, pi, ctl, remaining, j, tol);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                               int maxJ, float* V, float* W, BatchCtl* ctl, int* remaining,
                               long long j, double tol, hipStream_t s) {
-  if (n_tiles == 0) return hipSuccess;
-  return dispatch_kj_b(maxK, maxJ, [&](auto km, auto jm) {
-    constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
-    hipLaunchKernelGGL((batch_round_kernel<KM, JM>), dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles,
-                       V, W, ctl, remaining, j, tol);
-    return hipGetLastError();
-  });
+  return launch_round_t<VIOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, nullptr, ctl, remaining, j, tol, s);
+}
+
+hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
+                                   int maxJ, const uint8_t* pi, double* V, double* W, BatchCtl* ctl,
+                                   int* remaining, long long j, double tol, hipStream_t s) {
+  return launch_round_t<EvalOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, pi, ctl, remaining, j, tol, s);
+}
+
+hipError_t launch_batch_adjoint_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
+                                      int maxJ, const uint8_t* pi, float* w, float* W, BatchCtl* ctl,
+                                      int* remaining, long long j, double tol, hipStream_t s) {
+  return launch_round_t<AdjOp>(insts, tiles, n_tiles, maxK, maxJ, w, W, pi, ctl, remaining, j, tol, s);
+}
+
+template <typename T, ResKind RK>
+static hipError_t launch_finish_t(const BatchInst* insts, const int32_t* list, int n_list, T* V,
+                                  const T* W, BatchCtl* ctl, long long issued, BatchOut* out,
+                                  hipStream_t s) {
+  if (n_list == 0) return hipSuccess;
+  hipLaunchKernelGGL((batch_round_finish_kernel<T, RK>), dim3(64, n_list), dim3(256), 0, s, insts, list,
+                     n_list, V, W, ctl, issued, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_round_finish(const BatchInst* insts, const int32_t* list, int n_list,
                                      float* V, const float* W, BatchCtl* ctl, long long issued,
                                      BatchOut* out, hipStream_t s) {
-  if (n_list == 0) return hipSuccess;
-  hipLaunchKernelGGL(batch_round_finish_kernel, dim3(64, n_list), dim3(256), 0, s, insts, list, n_list,
-                     V, W, ctl, issued, out);
-  return hipGetLastError();
+  return launch_finish_t<float, ResKind::kMax>(insts, list, n_list, V, W, ctl, issued, out, s);
+}
+
+hipError_t launch_batch_eval_finish(const BatchInst* insts, const int32_t* list, int n_list,
+                                    double* V, const double* W, BatchCtl* ctl, long long issued,
+                                    BatchOut* out, hipStream_t s) {
+  return launch_finish_t<double, ResKind::kMax>(insts, list, n_list, V, W, ctl, issued, out, s);
+}
+
+hipError_t launch_batch_adjoint_finish(const BatchInst* insts, const int32_t* list, int n_list,
+                                       float* w, const float* W, BatchCtl* ctl, long long issued,
+                                       BatchOut* out, hipStream_t s) {
+  return launch_finish_t<float, ResKind::kSum>(insts, list, n_list, w, W, ctl, issued, out, s);
+}
+
+hipError_t launch_batch_extract(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
+                                int maxJ, const void* V, bool f64, uint8_t* pi, float* gap,
+                                hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  return dispatch_kj_b(maxK, maxJ, [&](auto km, auto jm) {
+    constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
+    if (f64)
+      hipLaunchKernelGGL((batch_extract_kernel<KM, JM, double>), dim3(n_tiles), dim3(kBlock), 0, s, insts,
+                         tiles, static_cast<const double*>(V), pi, gap);
+    else
+      hipLaunchKernelGGL((batch_extract_kernel<KM, JM, float>), dim3(n_tiles), dim3(kBlock), 0, s, insts,
+                         tiles, static_cast<const float*>(V), pi, gap);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_batch_greedy(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK, int maxJ,
+                               int kind, uint8_t* pi, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  return dispatch_kj_b(maxK, maxJ, [&](auto km, auto jm) {
+    constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
+    hipLaunchKernelGGL((batch_greedy_kernel<KM, JM>), dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles,
+                       kind, pi);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_batch_check(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK, int maxJ,
+                              const uint8_t* pi, int* flags, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  return dispatch_kj_b(maxK, maxJ, [&](auto km, auto jm) {
+    constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
+    hipLaunchKernelGGL((batch_check_kernel<KM, JM>), dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles, pi,
+                       flags);
+    return hipGetLastError();
+  });
+}
+
+size_t batch_grad_partial_doubles(int n_tiles, int maxJ) {
+  return static_cast<size_t>(n_tiles) * (2 * (maxJ <= 4 ? 4 : 8) + 2);
+}
+
+hipError_t launch_batch_grad(const BatchInst* insts, const Tile* tiles, int n_tiles, const int32_t* tile_begin,
+                             int n, int maxK, int maxJ, const uint8_t* pi, const double* V, const float* w,
+                             double* partial, double* out, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  return dispatch_kj_b(maxK, maxJ, [&](auto km, auto jm) {
+    constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
+    hipLaunchKernelGGL((batch_grad_partial_kernel<KM, JM>), dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles,
+                       pi, V, w, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((batch_grad_final_kernel<JM>), dim3(n), dim3(64), 0, s, insts, tile_begin, partial, V,
+                       out);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace mdpvi

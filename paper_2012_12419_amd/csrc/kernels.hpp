@@ -13,10 +13,16 @@ inline bool use_32bit_index(const Model& M) { return M.n_states < (int64_t{1} <<
 
 hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s);
 
-// V^{j+1} = T V^j (Vin -> Vout), residual into ctl->res[j % kResSlots];
-// a no-op once the stopping test has passed.
+// V^{j+1} = T V^j (Vin -> Vout), residual into the words of sweep j; a
+// no-op once the stopping test has passed.  slab_t > 0 selects the LDS slab
+// form with that many low digits per slab (see slab_digits), 0 the direct form.
 hipError_t launch_vi_sweep(const Model& M, const float* Vin, float* Vout, Ctl* ctl, long long j,
-                           double tol, hipStream_t s);
+                           double tol, hipStream_t s, int slab_t);
+
+// LDS bytes per slab and the fewest slabs (workgroups) a slab depth may leave.
+constexpr uint64_t kSlabLds = 40 * 1024;
+constexpr uint64_t kMinSlabs = 512;
+int slab_digits(const Model& M);
 
 // Greedy extraction from FP32 or FP64 values.
 hipError_t launch_extract_f32(const Model& M, const float* V, uint8_t* pi, float* gap,
@@ -52,12 +58,36 @@ hipError_t launch_objective(const Model& M, const double* V, double* out, hipStr
 hipError_t launch_batch_lds_vi(const BatchInst* insts, const int32_t* list, int n_list, int maxK,
                                int maxJ, size_t lds_bytes, float* V, double tol, long long max_iter,
                                BatchOut* out, hipStream_t s);
-hipError_t launch_batch_ctl_init(BatchCtl* ctl, int n, int* remaining, hipStream_t s);
+hipError_t launch_batch_ctl_init(BatchCtl* ctl, const int32_t* list, int n_list, int* remaining,
+                                 int* flags, int n_flags, hipStream_t s);
 hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                               int maxJ, float* V, float* W, BatchCtl* ctl, int* remaining,
                               long long j, double tol, hipStream_t s);
+hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
+                                   int maxJ, const uint8_t* pi, double* V, double* W, BatchCtl* ctl,
+                                   int* remaining, long long j, double tol, hipStream_t s);
+hipError_t launch_batch_adjoint_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
+                                      int maxJ, const uint8_t* pi, float* w, float* W, BatchCtl* ctl,
+                                      int* remaining, long long j, double tol, hipStream_t s);
 hipError_t launch_batch_round_finish(const BatchInst* insts, const int32_t* list, int n_list,
                                      float* V, const float* W, BatchCtl* ctl, long long issued,
                                      BatchOut* out, hipStream_t s);
+hipError_t launch_batch_eval_finish(const BatchInst* insts, const int32_t* list, int n_list,
+                                    double* V, const double* W, BatchCtl* ctl, long long issued,
+                                    BatchOut* out, hipStream_t s);
+hipError_t launch_batch_adjoint_finish(const BatchInst* insts, const int32_t* list, int n_list,
+                                       float* w, const float* W, BatchCtl* ctl, long long issued,
+                                       BatchOut* out, hipStream_t s);
+hipError_t launch_batch_extract(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
+                                int maxJ, const void* V, bool f64, uint8_t* pi, float* gap,
+                                hipStream_t s);
+hipError_t launch_batch_greedy(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK, int maxJ,
+                               int kind, uint8_t* pi, hipStream_t s);
+hipError_t launch_batch_check(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK, int maxJ,
+                              const uint8_t* pi, int* flags, hipStream_t s);
+size_t batch_grad_partial_doubles(int n_tiles, int maxJ);
+hipError_t launch_batch_grad(const BatchInst* insts, const Tile* tiles, int n_tiles, const int32_t* tile_begin,
+                             int n, int maxK, int maxJ, const uint8_t* pi, const double* V, const float* w,
+                             double* partial, double* out, hipStream_t s);
 
 }  // namespace mdpvi

@@ -55,6 +55,174 @@ __global__ __launch_bounds__(kBlock) void vi_sweep_kernel(Model M, const float* 
   block_max_to(dmax, ctl, j);
 }
 
+
+// ---------------------------------------------------------------- slab form
+//
+// The occupancy grid is cut into slabs: all occupancies that share the high
+// digits n_t..n_{K-1}.  A workgroup stages its slab's values (all J classes)
+// in LDS together with the arrival term A(o) = sum_j lambda_j/Lam V(o, j) of
+// every slab occupancy (FP64), so that every neighbour along the t low
+// digits (placements, releases, resets) is an LDS read; only neighbours along
+// the high digits are read from global memory, still contiguous per
+// wavefront.  The high digits are the same for the whole workgroup, so every
+// feasibility test along them is uniform.  The arithmetic and its order are
+// those of backup_occupancy: the two forms give bit-identical iterates.
+template <int KMAX, int JMAX>
+__global__ __launch_bounds__(kBlock) void vi_slab_kernel(Model M, int t, uint32_t slab_occ,
+                                                          const float* __restrict__ Vin,
+                                                          float* __restrict__ Vout, Ctl* ctl,
+                                                          long long j, double tol) {
+  if (sweep_stopped<ResKind::kMax>(ctl, j, tol)) return;
+  extern __shared__ double slab_lds[];
+  double* Al = slab_lds;                                     // [slab_occ]
+  float* Vl = reinterpret_cast<float*>(slab_lds + slab_occ);  // [J][slab_occ]
+  const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
+  const uint32_t slab = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t o0 = slab * slab_occ;
+  int nh[KMAX];
+  {
+    uint32_t q = slab;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      nh[k] = 0;
+      if (k >= t && k < M.K) {
+        const uint32_t q2 = fast_div(q, M.divR);
+        nh[k] = static_cast<int>(q - q2 * static_cast<uint32_t>(M.R));
+        q = q2;
+      }
+    }
+  }
+  for (uint32_t x = threadIdx.x; x < static_cast<uint32_t>(M.J) * slab_occ; x += kBlock) {
+    const uint32_t e = x / slab_occ;
+    const uint32_t ol = x - e * slab_occ;
+    Vl[x] = Vin[o0 + ol + e * nocc];
+  }
+  __syncthreads();
+  for (uint32_t ol = threadIdx.x; ol < slab_occ; ol += kBlock) {
+    double A = 0.0;
+#pragma unroll
+    for (int e = 0; e < JMAX; ++e)
+      if (e < M.J) A = fma(M.p[e], static_cast<double>(Vl[e * slab_occ + ol]), A);
+    Al[ol] = A;
+  }
+  __syncthreads();
+
+  double dmax = 0.0;
+  for (uint32_t ol = threadIdx.x; ol < slab_occ; ol += kBlock) {
+    const uint32_t o = o0 + ol;
+    int n[KMAX];
+    {
+      uint32_t q = ol;
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < t) {
+          const uint32_t q2 = fast_div(q, M.divR);
+          n[k] = static_cast<int>(q - q2 * static_cast<uint32_t>(M.R));
+          q = q2;
+        } else {
+          n[k] = nh[k];
+        }
+      }
+    }
+    int load = 0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) load += n[k];
+    const double a_rej = Al[ol];
+    double a_best[JMAX];
+    bool any[JMAX];
+#pragma unroll
+    for (int u = 0; u < JMAX; ++u) {
+      a_best[u] = 0.0;
+      any[u] = false;
+    }
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a) {
+      if (a < M.K) {
+#pragma unroll
+        for (int u = 0; u < JMAX; ++u) {
+          if (u < M.n_sizes && n[a] + M.size_u[u] <= M.C) {
+            const uint32_t off = static_cast<uint32_t>(M.size_u[u]) * static_cast<uint32_t>(M.stride[a]);
+            double A;
+            if (a < t) {
+              A = Al[ol + off];
+            } else {
+              A = 0.0;
+              const uint32_t m = o + off;
+#pragma unroll
+              for (int jj = 0; jj < JMAX; ++jj)
+                if (jj < M.J) A = fma(M.p[jj], static_cast<double>(Vin[m + jj * nocc]), A);
+            }
+            if (!any[u] || A > a_best[u]) a_best[u] = A;
+            any[u] = true;
+          }
+        }
+      }
+    }
+    const double idle = M.mu_L * static_cast<double>(M.KC - load);
+#pragma unroll
+    for (int e = 0; e < JMAX; ++e) {
+      if (e < M.J) {
+        const uint32_t gbase = o + e * nocc;
+        const uint32_t lbase = ol + e * slab_occ;
+        const float vse = Vl[lbase];
+        double D = idle * static_cast<double>(vse);
+        double rs = 0.0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+          if (k < M.K) {
+            const uint32_t st = static_cast<uint32_t>(M.stride[k]);
+            if (k < t) {
+              if (n[k] > 0) D = fma(M.mu_L * n[k], static_cast<double>(Vl[lbase - st]), D);
+              rs += static_cast<double>(Vl[lbase - static_cast<uint32_t>(n[k]) * st]);
+            } else {
+              if (n[k] > 0) D = fma(M.mu_L * n[k], static_cast<double>(Vin[gbase - st]), D);
+              float v = vse;
+              if (n[k] > 0) v = Vin[gbase - static_cast<uint32_t>(n[k]) * st];
+              rs += static_cast<double>(v);
+            }
+          }
+        }
+        D = fma(M.nu_L, rs, D);
+        double best = fma(M.gamma, a_rej, M.r_reject[e]);
+        const int u = M.size_idx[e];
+        double ab = 0.0;
+        bool an = false;
+#pragma unroll
+        for (int uu = 0; uu < JMAX; ++uu)
+          if (uu == u) {
+            ab = a_best[uu];
+            an = any[uu];
+          }
+        if (an) {
+          const double q = fma(M.gamma, ab, M.r_place[e]);
+          if (q > best) best = q;
+        }
+        const float vn = static_cast<float>(fma(M.gamma, D, best));
+        Vout[gbase] = vn;
+        const double d = fabs(static_cast<double>(vn) - static_cast<double>(vse));
+        dmax = (d > dmax || d != d) ? d : dmax;
+      }
+    }
+  }
+  block_max_to(dmax, ctl, j);
+}
+
+// Slab depth for M: the most low digits t whose slab (values of all classes
+// in FP32 plus the FP64 arrival term) fits kSlabLds bytes while leaving at
+// least kMinSlabs workgroups; 0 when no t >= 1 qualifies (use the direct form).
+int slab_digits(const Model& M) {
+  if (!use_32bit_index(M)) return 0;
+  int best = 0;
+  uint64_t occ = 1;
+  for (int t = 1; t < M.K; ++t) {
+    occ *= static_cast<uint64_t>(M.R);
+    const uint64_t bytes = occ * (8 + 4 * static_cast<uint64_t>(M.J));
+    const uint64_t slabs = static_cast<uint64_t>(M.n_occ) / occ;
+    if (bytes <= kSlabLds && slabs >= kMinSlabs) best = t;
+  }
+  return best;
+}
+
 __global__ void ctl_init_kernel(Ctl* ctl) {
   if (threadIdx.x == 0) {
     ctl->done_iter = -1;
@@ -79,6 +247,18 @@ static hipError_t launch_sweep_t(const Model& M, const float* Vin, float* Vout, 
   return hipGetLastError();
 }
 
+template <int KMAX, int JMAX>
+static hipError_t launch_slab_t(const Model& M, int t, const float* Vin, float* Vout, Ctl* ctl,
+                                long long j, double tol, hipStream_t s) {
+  uint32_t slab_occ = 1;
+  for (int k = 0; k < t; ++k) slab_occ *= static_cast<uint32_t>(M.R);
+  const uint32_t grid = static_cast<uint32_t>(M.n_occ / slab_occ);
+  const size_t lds = static_cast<size_t>(slab_occ) * (8 + 4 * M.J);
+  hipLaunchKernelGGL((vi_slab_kernel<KMAX, JMAX>), dim3(grid), dim3(kBlock), lds, s, M, t, slab_occ,
+                     Vin, Vout, ctl, j, tol);
+  return hipGetLastError();
+}
+
 template <typename Idx>
 static hipError_t launch_sweep_idx(const Model& M, const float* Vin, float* Vout, Ctl* ctl,
                                    long long j, double tol, hipStream_t s) {
@@ -93,7 +273,17 @@ static hipError_t launch_sweep_idx(const Model& M, const float* Vin, float* Vout
 }
 
 hipError_t launch_vi_sweep(const Model& M, const float* Vin, float* Vout, Ctl* ctl, long long j,
-                           double tol, hipStream_t s) {
+                           double tol, hipStream_t s, int slab_t) {
+  if (slab_t > 0) {
+    if (M.J <= 4) {
+      if (M.K <= 4) return launch_slab_t<4, 4>(M, slab_t, Vin, Vout, ctl, j, tol, s);
+      if (M.K <= 8) return launch_slab_t<8, 4>(M, slab_t, Vin, Vout, ctl, j, tol, s);
+      return launch_slab_t<16, 4>(M, slab_t, Vin, Vout, ctl, j, tol, s);
+    }
+    if (M.K <= 4) return launch_slab_t<4, 8>(M, slab_t, Vin, Vout, ctl, j, tol, s);
+    if (M.K <= 8) return launch_slab_t<8, 8>(M, slab_t, Vin, Vout, ctl, j, tol, s);
+    return launch_slab_t<16, 8>(M, slab_t, Vin, Vout, ctl, j, tol, s);
+  }
   if (use_32bit_index(M)) return launch_sweep_idx<uint32_t>(M, Vin, Vout, ctl, j, tol, s);
   return launch_sweep_idx<uint64_t>(M, Vin, Vout, ctl, j, tol, s);
 }

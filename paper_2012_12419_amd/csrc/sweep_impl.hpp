@@ -74,8 +74,16 @@ __device__ __forceinline__ double backup_occupancy(const Model& M, const float* 
       D = fma(M.nu_L, rs, D);
       double best = fma(M.gamma, a_rej, M.r_reject[e]);
       const int u = M.size_idx[e];
-      if (any[u]) {
-        const double q = fma(M.gamma, a_best[u], M.r_place[e]);
+      double ab = 0.0;
+      bool an = false;
+#pragma unroll
+      for (int uu = 0; uu < JMAX; ++uu)
+        if (uu == u) {
+          ab = a_best[uu];
+          an = any[uu];
+        }
+      if (an) {
+        const double q = fma(M.gamma, ab, M.r_place[e]);
         if (q > best) best = q;
       }
       const float vn = static_cast<float>(fma(M.gamma, D, best));

@@ -1,0 +1,94 @@
+"""GPU parity of the batched gradient and greedy-scoring pipeline.
+
+For every instance of a mixed batch: value iteration -> extraction -> FP64
+evaluation -> one FP64 improvement step -> adjoint gradient, and the
+least-loaded greedy policy with its FP64 value.  Checked against the FP64
+oracle instance by instance, and against the single-instance entry points
+bit for bit (same per-state arithmetic, same tile order in the reductions).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import grad, vi
+from tests.gpu_util import EVAL_REL, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mdpvi():
+    torch_cuda()
+    import paper_2012_12419_amd as m
+    m.load()
+    return m
+
+
+def _instances():
+    out = list(W.batch(10, seed=5))
+    out.append(W.gradient_instance(3, 6))
+    out.append(W.make(4, 8, (1, 2), (1.2, 0.6), 0.1, 0.02, (1.0, 2.5), 0.97))        # 13,122 states
+    out.append(W.make(2, 5, (1, 2), (0.9, 0.5), 0.1, 0.02, (0.3, 4.0), 0.95, reject_cost=(0.2, 0.5)))
+    return out
+
+
+def _batch_pipeline(mdpvi, insts):
+    import torch
+    b = mdpvi.Batch(insts)
+    N = b.num_states
+    V = torch.zeros(N, device="cuda")
+    lb = torch.zeros(N, device="cuda")
+    for i, p in enumerate(insts):   # constant sub-solution start for instances with reject costs
+        lam = np.asarray(p.lam)
+        Lam = lam.sum() + p.K * p.C * p.mu + p.K * p.nu
+        lb[b.offsets[i]:b.offsets[i + 1]] = -lam.sum() / Lam * max(p.reject_cost) / (1 - p.gamma)
+    V.copy_(lb)
+    b.vi_solve(V, tol=1e-7)
+    pi, _ = b.policy_extract(V, want_gap=False)
+    Vp = V.double()
+    b.policy_eval(pi, Vp, tol=1e-12)
+    pi2, _ = b.policy_extract(Vp, want_gap=False)
+    if not torch.equal(pi2, pi):
+        pi = pi2
+        b.policy_eval(pi, Vp, tol=1e-12)
+    grads, objs, w, st, its = b.vi_adjoint(pi, Vp, [p.J for p in insts], tol=1e-11)
+    pig = b.policy_greedy("least_loaded")
+    Vg, _, _, _ = b.policy_eval(pig, tol=1e-12)
+    return b, pi, Vp, grads, objs, w, pig, Vg
+
+
+def test_batch_gradient_and_greedy_vs_oracle(mdpvi):
+    insts = _instances()
+    b, pi, Vp, grads, objs, w, pig, Vg = _batch_pipeline(mdpvi, insts)
+    pi_h, Vp_h, pig_h, Vg_h = (t.cpu().numpy() for t in (pi, Vp, pig, Vg))
+    for i, p in enumerate(insts):
+        sl = slice(b.offsets[i], b.offsets[i + 1])
+        print(f"instance {i}: K={p.K} C={p.C} J={p.J} N={p.num_states}", flush=True)
+        g = vi.grid(p)
+        star = vi.value_iteration(p, 1e-13, g=g).V
+        pi_o, _ = vi.extract(p, star, g)
+        V_o = vi.policy_eval(p, pi_o, tol=1e-13, g=g)
+        assert np.array_equal(pi_h[sl], pi_o)
+        assert np.max(np.abs(Vp_h[sl] - V_o)) <= EVAL_REL * np.max(np.abs(V_o))
+        assert abs(objs[i] - vi.objective(p, V_o)) <= 1e-10 * max(1.0, abs(objs[i]))
+        g_o = grad.gradient_adjoint(p, pi_o, V=V_o)
+        assert np.max(np.abs(np.array(grads[i]) - g_o)) <= 1e-5 * np.max(np.abs(g_o))
+        pg_o = vi.greedy_policy(p, "least_loaded", g)
+        assert np.array_equal(pig_h[sl], pg_o)
+        Vg_o = vi.policy_eval(p, pg_o, tol=1e-13, g=g)
+        assert np.max(np.abs(Vg_h[sl] - Vg_o)) <= EVAL_REL * np.max(np.abs(Vg_o))
+        assert np.all(Vg_h[sl] <= Vp_h[sl] + 1e-9 * np.max(np.abs(V_o)))
+
+
+def test_batch_gradient_equals_single_instance(mdpvi):
+    import torch
+    insts = _instances()
+    b, pi, Vp, grads, objs, w, pig, Vg = _batch_pipeline(mdpvi, insts)
+    for i, p in enumerate(insts):
+        sl = slice(b.offsets[i], b.offsets[i + 1])
+        mdp = mdpvi.MDP.from_instance(p)
+        g1, J1, w1, _ = mdp.vi_adjoint(pi[sl].contiguous(), Vp[sl].contiguous(), tol=1e-11)
+        assert np.array_equal(np.array(g1), np.array(grads[i])), i
+        assert np.array_equal(w1.cpu().numpy().view(np.uint32), w[sl].cpu().numpy().view(np.uint32)), i
+        V1, _ = mdp.policy_eval(pig[sl].contiguous(), tol=1e-12)
+        assert np.array_equal(V1.cpu().numpy().view(np.uint64), Vg[sl].cpu().numpy().view(np.uint64)), i

@@ -221,3 +221,59 @@ def test_gradient_config_size(mdpvi):
 
 def test_large_single_instance(mdpvi):
     _full_size_check(mdpvi, W.large_single())
+
+
+FORM_CASES = [("small_parity", W.small_parity()),
+              ("ragged_K4C12J3", W.make(4, 12, (1, 2, 3), (0.6, 0.5, 0.3), 0.08, 0.02, (1.0, 2.1, 3.3), 0.97)),
+              ("K16_C1", W.make(16, 1, (1,), (1.5,), 0.1, 0.01, (1.0,), 0.9)),
+              ("J8_K3C8", W.make(3, 8, tuple(range(1, 9)), [0.1 * (j + 1) for j in range(8)], 0.1, 0.02,
+                                 [0.8 * (j + 1) for j in range(8)], 0.9)),
+              ("gradient", W.gradient_instance())]
+
+
+@pytest.mark.parametrize("name,inst", FORM_CASES, ids=[c[0] for c in FORM_CASES])
+def test_sweep_forms_bit_identical(mdpvi, name, inst):
+    # every sweep kernel form computes the same arithmetic in the same order
+    import torch
+    mdp = mdpvi.MDP.from_instance(inst)
+    forms = [0]
+    occ = 1
+    for t in range(1, inst.K):
+        occ *= inst.C + 1
+        if occ * (8 + 4 * inst.J) <= 64 * 1024:
+            forms.append(t)
+    ref = None
+    for f in forms + [-1]:
+        mdp.set_sweep_form(f)
+        V = torch.zeros(mdp.num_states, device="cuda")
+        st = mdp.vi_solve(V, tol=1e-7)
+        got = (V.cpu().numpy().view(np.uint32).copy(), st["iterations"])
+        print(f"{name}: form {f}: {st['iterations']} sweeps", flush=True)
+        if ref is None:
+            ref = got
+            star = vi.value_iteration(inst, 1e-12).V if inst.num_states < 400_000 else None
+            if star is not None:
+                vi_close(V.cpu().numpy(), star)
+        else:
+            assert got[1] == ref[1]
+            assert np.array_equal(got[0], ref[0])
+
+
+def test_autotune_cache(mdpvi, tmp_path):
+    import json
+    import os
+    import torch
+    path = tmp_path / "tune.json"
+    os.environ["MDPVI_AUTOTUNE_CACHE"] = str(path)
+    try:
+        inst = W.gradient_instance()
+        mdp = mdpvi.MDP.from_instance(inst)
+        form, us = mdp.autotune(trials=5)
+        assert form >= 0 and us > 0
+        data = json.loads(path.read_text())
+        key = [k for k in data if "K=5|C=10|J=2|S=1,2" in k]
+        assert len(key) == 1 and data[key[0]][0] == form
+        V = torch.zeros(mdp.num_states, device="cuda")
+        mdp.vi_solve(V, tol=1e-6)
+    finally:
+        del os.environ["MDPVI_AUTOTUNE_CACHE"]
