@@ -31,7 +31,7 @@ class MdpValue(torch.autograd.Function):
         mdp.vi_solve(V, tol=spec.get("tol", 1e-6))
         pi, _ = mdp.policy_extract(V, want_gap=False)
         Vp = V.double()
-        for _ in range(spec.get("improve_steps", 4)):
+        for _ in range(spec.get("improve_steps", 8)):
             mdp.policy_eval(pi, Vp, tol=spec.get("eval_tol", 1e-11))
             pi2, _ = mdp.policy_extract(Vp, want_gap=False)
             if torch.equal(pi2, pi):

@@ -33,8 +33,8 @@ template <int KMAX, int JMAX, typename Idx>
 __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(Model M, const uint8_t* __restrict__ pi,
                                                                 const float* __restrict__ win,
                                                                 float* __restrict__ wout, Ctl* ctl,
-                                                                long long j, double tol) {
-  if (sweep_stopped<ResKind::kSum>(ctl, j, tol)) return;
+                                                                double* res, long long j, double tol) {
+  if (sweep_stopped<ResKind::kSum>(ctl, res, j, tol)) return;
   const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
   const Idx base = static_cast<Idx>(b) * (kBlock * kOccPerThread) + threadIdx.x;
   double dsum = 0.0;
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(Model M, const ui
     const Idx o = base + static_cast<Idx>(i * kBlock);
     if (o < static_cast<Idx>(M.n_occ)) dsum += adjoint_occupancy<KMAX, JMAX>(M, pi, win, wout, o);
   }
-  block_sum_to(dsum, ctl, j);
+  block_sum_to(dsum, res, j);
 }
 
 // Number of gradient entries: lambda_1..J, mu, nu, r_1..J.
@@ -161,15 +161,15 @@ size_t grad_partial_doubles(const Model& M) {
 }
 
 hipError_t launch_adjoint_sweep(const Model& M, const uint8_t* pi, const float* win, float* wout,
-                                Ctl* ctl, long long j, double tol, hipStream_t s) {
+                                Ctl* ctl, double* res, long long j, double tol, hipStream_t s) {
   return dispatch_kj(M, [&](auto km, auto jm) {
     constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
     if (use_32bit_index(M)) {
       hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint32_t>), dim3(sweep_blocks(M)), dim3(kBlock),
-                         0, s, M, pi, win, wout, ctl, j, tol);
+                         0, s, M, pi, win, wout, ctl, res, j, tol);
     } else {
       hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint64_t>), dim3(sweep_blocks(M)), dim3(kBlock),
-                         0, s, M, pi, win, wout, ctl, j, tol);
+                         0, s, M, pi, win, wout, ctl, res, j, tol);
     }
     return hipGetLastError();
   });

@@ -34,8 +34,12 @@ struct mdpvi_mdp {
   int device = -1;              // device of the scratch below (-1: none yet)
   void* vbuf = nullptr;         // second value buffer (ping-pong partner)
   size_t vbuf_bytes = 0;
+  double* abuf = nullptr;       // two FP64 arrival-term arrays (exact-shape direct form)
   Ctl* ctl = nullptr;           // device control words
   Ctl* ctl_host = nullptr;      // pinned mirror
+  double* res = nullptr;        // residual words / per-workgroup partials
+  double* res_host = nullptr;   // pinned, res_n doubles
+  size_t res_n = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double* aux = nullptr;        // gradient partials and outputs
   size_t aux_bytes = 0;
@@ -96,6 +100,22 @@ int ensure_scratch(mdpvi_mdp* h, size_t bytes) {
     }
     HIP_TRY(hipEventCreate(&h->ev0));
     HIP_TRY(hipEventCreate(&h->ev1));
+    // the largest grid of any sweep form: the direct form, or the slab form
+    // with one low digit (n_occ / (C+1) workgroups)
+    const uint64_t g1 = static_cast<uint64_t>(h->M.n_occ) / static_cast<uint64_t>(h->M.R);
+    const uint32_t gmax = std::max<uint32_t>(
+        std::max(std::max(mdpvi::occ_sweep_grid(h->M), mdpvi::eval_sweep_grid(h->M)), mdpvi::vi_sweep_grid(h->M, 0)),
+        static_cast<uint32_t>(g1));
+    h->res_n = mdpvi::res_doubles(gmax);
+    if (hipMalloc(reinterpret_cast<void**>(&h->res), h->res_n * sizeof(double)) != hipSuccess) {
+      h->res = nullptr;
+      return fail(MDPVI_ENOMEM, "hipMalloc of %zu residual words failed", h->res_n);
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->res_host), h->res_n * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+      h->res_host = nullptr;
+      return fail(MDPVI_ENOMEM, "hipHostMalloc of the residual mirror failed");
+    }
     h->device = dev;
   }
   if (bytes > h->vbuf_bytes) {
@@ -147,16 +167,32 @@ double bits_to_double(unsigned long long b) {
   return d;
 }
 
-// Residual of sweep j from its partial words (max of the lanes, or their sum
-// for 1-norm residuals); a NaN lane makes the result NaN.
-double residual_of(const Ctl* c, long long j, bool sum) {
+// Final residual of sweep j, read from the device: the max over the grid
+// workgroup maxima (max norm) or the sum of the kResLanes words (1-norm); a
+// NaN anywhere makes the result NaN.
+int final_residual(mdpvi_mdp* h, long long j, bool sum, uint32_t grid, hipStream_t s, double* out) {
   double r = 0.0;
-  for (int l = 0; l < mdpvi::kResLanes; ++l) {
-    const double v = bits_to_double(c->res[j % mdpvi::kResSlots][l][0]);
-    if (std::isnan(v)) return v;
-    r = sum ? r + v : std::max(r, v);
+  if (sum) {
+    HIP_TRY(hipMemcpy2DAsync(h->res_host, sizeof(double), h->res + mdpvi::sum_word(j, 0),
+                             mdpvi::kSumStride * sizeof(double), sizeof(double), mdpvi::kResLanes,
+                             hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int l = 0; l < mdpvi::kResLanes; ++l) r += h->res_host[l];
+  } else {
+    HIP_TRY(hipMemcpyAsync(h->res_host, h->res + static_cast<size_t>(j % mdpvi::kResSlots) * grid,
+                           grid * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (uint32_t b = 0; b < grid; ++b) {
+      const double v = h->res_host[b];
+      if (std::isnan(v)) {
+        r = v;
+        break;
+      }
+      r = std::max(r, v);
+    }
   }
-  return r;
+  *out = r;
+  return MDPVI_OK;
 }
 
 // Enqueue sweeps j = 0, 1, ... in chunks until the device reports the test
@@ -165,9 +201,9 @@ double residual_of(const Ctl* c, long long j, bool sum) {
 template <typename T, typename Sweep>
 int run_loop(mdpvi_mdp* h, T* buf0, double tol, int64_t max_iter, hipStream_t s,
              mdpvi_stats* st, double bytes_per_sweep, double backups_per_sweep, Sweep sweep,
-             bool sum_residual = false) {
+             bool sum_residual, uint32_t grid) {
   T* buf[2] = {buf0, static_cast<T*>(h->vbuf)};
-  HIP_TRY(mdpvi::launch_ctl_init(h->ctl, s));
+  HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));
   HIP_TRY(hipEventRecord(h->ev0, s));
   if (h->timing && !h->sweep_ev) {
     h->sweep_ev = new (std::nothrow) hipEvent_t[2 * kMaxChunk]();
@@ -205,7 +241,10 @@ int run_loop(mdpvi_mdp* h, T* buf0, double tol, int64_t max_iter, hipStream_t s,
   double res;
   bool converged;
   final_iter = done >= 0 ? done : issued;
-  res = residual_of(h->ctl_host, final_iter - 1, sum_residual);
+  {
+    int rc = final_residual(h, final_iter - 1, sum_residual, grid, s, &res);
+    if (rc) return rc;
+  }
   converged = res < tol;
   if (final_iter & 1) {
     HIP_TRY(hipMemcpyAsync(buf0, buf[1], static_cast<size_t>(h->M.n_states) * sizeof(T),
@@ -444,8 +483,11 @@ int mdp_build(const mdpvi_params* p, mdpvi_mdp_t* out) {
 void mdp_free(mdpvi_mdp_t h) {
   if (!h) return;
   if (h->vbuf) (void)hipFree(h->vbuf);
+  if (h->abuf) (void)hipFree(h->abuf);
   if (h->ctl) (void)hipFree(h->ctl);
   if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+  if (h->res) (void)hipFree(h->res);
+  if (h->res_host) (void)hipHostFree(h->res_host);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   if (h->aux) (void)hipFree(h->aux);
@@ -497,17 +539,28 @@ int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream
     }
   }
   float* out = static_cast<float*>(h->vbuf);
+  double* A[2] = {nullptr, nullptr};
+  if (mdpvi::exact_shape(M)) {
+    if (!h->abuf && hipMalloc(reinterpret_cast<void**>(&h->abuf), 2 * (M.n_occ + 1) * sizeof(double)) != hipSuccess) {
+      h->abuf = nullptr;
+      return fail(MDPVI_ENOMEM, "hipMalloc of the arrival-term arrays failed");
+    }
+    A[0] = h->abuf;
+    A[1] = h->abuf + M.n_occ + 1;
+    HIP_TRY(mdpvi::launch_arrival_init(M, V, A[0], A[1], s));
+  }
   int best = 0;
   double best_t = 1e300;
   for (int form : forms) {
+    double* const* Af = (form == 0 && A[0]) ? A : nullptr;
     // sweep 0 (no stopping test) from V into the scratch buffer, untimed once
-    HIP_TRY(mdpvi::launch_ctl_init(h->ctl, s));
-    HIP_TRY(mdpvi::launch_vi_sweep(M, V, out, h->ctl, 0, 1.0, s, form));
+    HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));
+    HIP_TRY(mdpvi::launch_vi_sweep(M, V, out, h->ctl, h->res, 0, 1.0, s, form, Af));
     std::vector<float> ms(trials);
     for (int r = 0; r < trials; ++r) {
-      HIP_TRY(mdpvi::launch_ctl_init(h->ctl, s));
+      HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));
       HIP_TRY(hipEventRecord(h->ev0, s));
-      HIP_TRY(mdpvi::launch_vi_sweep(M, V, out, h->ctl, 0, 1.0, s, form));
+      HIP_TRY(mdpvi::launch_vi_sweep(M, V, out, h->ctl, h->res, 0, 1.0, s, form, Af));
       HIP_TRY(hipEventRecord(h->ev1, s));
       HIP_TRY(hipEventSynchronize(h->ev1));
       HIP_TRY(hipEventElapsedTime(&ms[r], h->ev0, h->ev1));
@@ -546,13 +599,25 @@ int vi_solve(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, void* hip_st
   int slab_t = h->slab_t;
   if (slab_t < 0) {
     const int cached = tune_lookup(M);
-    slab_t = cached >= 0 ? cached : mdpvi::slab_digits(M);
+    slab_t = cached >= 0 ? cached : (mdpvi::exact_shape(M) ? 0 : mdpvi::slab_digits(M));
+  }
+  double* A[2] = {nullptr, nullptr};
+  if (slab_t == 0 && mdpvi::exact_shape(M)) {
+    if (!h->abuf && hipMalloc(reinterpret_cast<void**>(&h->abuf), 2 * (M.n_occ + 1) * sizeof(double)) != hipSuccess) {
+      h->abuf = nullptr;
+      return fail(MDPVI_ENOMEM, "hipMalloc of the arrival-term arrays failed");
+    }
+    A[0] = h->abuf;
+    A[1] = h->abuf + M.n_occ + 1;
+    HIP_TRY(mdpvi::launch_arrival_init(M, V, A[0], A[1], s));
   }
   return run_loop<float>(h, V, tol, max_iter, s, st, 8.0 * M.n_states,
                          static_cast<double>(h->feasible_pairs),
                          [&](long long j, float* in, float* out) {
-                           return mdpvi::launch_vi_sweep(M, in, out, h->ctl, j, tol, s, slab_t);
-                         });
+                           return mdpvi::launch_vi_sweep(M, in, out, h->ctl, h->res, j, tol, s, slab_t,
+                                                         A[0] ? A : nullptr);
+                         },
+                         false, mdpvi::vi_sweep_grid(M, slab_t));
 }
 
 int policy_extract(mdpvi_mdp_t h, const float* V, uint8_t* pi, float* gap, void* hip_stream) {
@@ -576,7 +641,7 @@ int policy_eval(mdpvi_mdp_t h, const uint8_t* pi, double* V, double tol, int64_t
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const Model& M = h->M;
-  HIP_TRY(mdpvi::launch_ctl_init(h->ctl, s));
+  HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));
   HIP_TRY(mdpvi::launch_policy_check(M, pi, h->ctl, s));
   HIP_TRY(hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -585,8 +650,9 @@ int policy_eval(mdpvi_mdp_t h, const uint8_t* pi, double* V, double tol, int64_t
   return run_loop<double>(h, V, tol, max_iter, s, st, 17.0 * M.n_states,
                           static_cast<double>(M.n_states),
                           [&](long long j, double* in, double* out) {
-                            return mdpvi::launch_eval_sweep(M, pi, in, out, h->ctl, j, tol, s);
-                          });
+                            return mdpvi::launch_eval_sweep(M, pi, in, out, h->ctl, h->res, j, tol, s);
+                          },
+                          false, mdpvi::eval_sweep_grid(M));
 }
 
 int vi_adjoint(mdpvi_mdp_t h, const uint8_t* pi, const double* V_pi, float* w, double* grad,
@@ -603,7 +669,7 @@ int vi_adjoint(mdpvi_mdp_t h, const uint8_t* pi, const double* V_pi, float* w, d
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const Model& M = h->M;
-  HIP_TRY(mdpvi::launch_ctl_init(h->ctl, s));
+  HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));
   HIP_TRY(mdpvi::launch_policy_check(M, pi, h->ctl, s));
   HIP_TRY(hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -612,9 +678,9 @@ int vi_adjoint(mdpvi_mdp_t h, const uint8_t* pi, const double* V_pi, float* w, d
   rc = run_loop<float>(
       h, w, tol, max_iter, s, st, 9.0 * M.n_states, static_cast<double>(M.n_states),
       [&](long long j, float* in, float* out) {
-        return mdpvi::launch_adjoint_sweep(M, pi, in, out, h->ctl, j, tol, s);
+        return mdpvi::launch_adjoint_sweep(M, pi, in, out, h->ctl, h->res, j, tol, s);
       },
-      /*sum_residual=*/true);
+      /*sum_residual=*/true, mdpvi::occ_sweep_grid(M));
   if (rc != MDPVI_OK && rc != MDPVI_ENOCONV) return rc;
   double* out_dev = h->aux + npart;
   HIP_TRY(mdpvi::launch_grad(M, pi, V_pi, w, h->aux, out_dev, s));

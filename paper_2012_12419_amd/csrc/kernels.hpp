@@ -11,13 +11,23 @@ namespace mdpvi {
 // neighbour offset fits in 31 bits.
 inline bool use_32bit_index(const Model& M) { return M.n_states < (int64_t{1} << 31); }
 
-hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s);
+hipError_t launch_ctl_init(Ctl* ctl, double* res, hipStream_t s);
 
 // V^{j+1} = T V^j (Vin -> Vout), residual into the words of sweep j; a
 // no-op once the stopping test has passed.  slab_t > 0 selects the LDS slab
 // form with that many low digits per slab (see slab_digits), 0 the direct form.
-hipError_t launch_vi_sweep(const Model& M, const float* Vin, float* Vout, Ctl* ctl, long long j,
-                           double tol, hipStream_t s, int slab_t);
+// A: the two FP64 arrival-term arrays (n_occ + 1 doubles each) of the
+// exact-shape direct form (sweep j reads A[j % 2], writes A[(j + 1) % 2]);
+// NULL uses the forms without them.
+hipError_t launch_vi_sweep(const Model& M, const float* Vin, float* Vout, Ctl* ctl, double* res,
+                           long long j, double tol, hipStream_t s, int slab_t, double* const* A);
+// True when the exact-shape direct form (with arrival-term arrays) applies.
+bool exact_shape(const Model& M);
+// A0(o) = sum_e lambda_e/Lam V(o, e) for every occupancy; A0[n_occ] =
+// A1[n_occ] = -inf (each array holds n_occ + 1 doubles).
+hipError_t launch_arrival_init(const Model& M, const float* V, double* A0, double* A1, hipStream_t s);
+// Workgroups of one value-iteration sweep in the given form.
+uint32_t vi_sweep_grid(const Model& M, int slab_t);
 
 // LDS bytes per slab and the fewest slabs (workgroups) a slab depth may leave.
 constexpr uint64_t kSlabLds = 40 * 1024;
@@ -35,14 +45,18 @@ hipError_t launch_policy_check(const Model& M, const uint8_t* pi, Ctl* ctl, hipS
 
 // One fixed-policy FP64 sweep V^{j+1} = r_pi + gamma P_pi V^j.
 hipError_t launch_eval_sweep(const Model& M, const uint8_t* pi, const double* Vin, double* Vout,
-                             Ctl* ctl, long long j, double tol, hipStream_t s);
+                             Ctl* ctl, double* res, long long j, double tol, hipStream_t s);
+// Workgroups of one generic-form evaluation or adjoint sweep (4 occupancies
+// per thread), and of the evaluation sweep actually launched.
+uint32_t occ_sweep_grid(const Model& M);
+uint32_t eval_sweep_grid(const Model& M);
 
 // Greedy heuristic policies (0 least-loaded, 1 first-fit).
 hipError_t launch_greedy(const Model& M, int kind, uint8_t* pi, hipStream_t s);
 
 // One transposed (adjoint) sweep w^{j+1} = c + gamma P_pi^T w^j, 1-norm residual.
 hipError_t launch_adjoint_sweep(const Model& M, const uint8_t* pi, const float* win, float* wout,
-                                Ctl* ctl, long long j, double tol, hipStream_t s);
+                                Ctl* ctl, double* res, long long j, double tol, hipStream_t s);
 
 // Doubles of workgroup partials needed by launch_grad.
 size_t grad_partial_doubles(const Model& M);

@@ -21,8 +21,9 @@ constexpr int kOccPerThread = 4;  // occupancies per thread in the sweep kernels
 constexpr int kMaxK = 16;
 constexpr int kMaxJ = 8;
 constexpr int kResSlots = 4;    // ring of per-sweep residuals
-constexpr int kResLanes = 64;   // words per residual: workgroup b reduces into word b % 64
-constexpr int kResStride = 16;  // one word per 128-byte line (64-bit words)
+constexpr int kResLanes = 64;   // words of a 1-norm residual: workgroup b adds into word b % 64
+constexpr int kResStride = 16;  // 64-bit words per 128-byte line (batched control blocks)
+constexpr int kSumStride = 544; // doubles between 1-norm words (17 x 256 bytes: distinct channels)
 
 // Unsigned 32-bit division by a run-time constant d >= 2 with one high
 // multiply, a subtract, an add and two shifts (Granlund & Montgomery, "Division
@@ -81,27 +82,44 @@ struct Model {
   double mu, nu, Lam, lam_tot;
 };
 
-// Control words of one iterative solve, in device memory.
+// Control words of one iterative solve, in device memory (copied to the host
+// once per chunk of sweeps).
 //   done_iter: -1 while running; else the index k of the first iterate V^k
 //              whose residual ||V^k - V^{k-1}|| passed the test (or was NaN).
 //   flag:      set by validation kernels (an infeasible policy entry).
-//   res:       the residual of the sweep with index j lives in ring slot
-//              r = j mod kResSlots as kResLanes partial words, one per
-//              128-byte line so that concurrent atomics from different
-//              workgroups do not queue on one address; the residual is the
-//              max (or, for 1-norm residuals, the sum) of the lanes.  A word
-//              holds the bit pattern of a non-negative double: such doubles
-//              order like their bit patterns, so atomicMax on the bits is a
-//              max, and NaN patterns order above +inf.
+//   go[r][x]:  the sweep with index j (r = j mod kResSlots) failed the test in
+//              some workgroup b with b mod 8 = x: that workgroup's largest
+//              |V' - V| is not below tol.  Workgroups raise it with a plain
+//              store only after reading it still clear, so a word sees a few
+//              stores per sweep instead of one per workgroup (stores to one
+//              address from thousands of workgroups serialise in the memory
+//              system).  Workgroups b and b + 8 normally share an XCD and
+//              hence its L2.  The sweep converged iff every go[r][x] is clear.
+//   nan[r][x]: likewise for a NaN.  Every word sits on its own 128-byte line.
+// The residual values themselves live in a separate buffer.
 struct Ctl {
   long long done_iter;
   long long flag;
-  long long pad[kResStride - 2];
-  unsigned long long res[kResSlots][kResLanes][kResStride];
+  long long pad[14];
+  unsigned int go[kResSlots][kNumXcd][32];
+  unsigned int nan[kResSlots][kNumXcd][32];
 };
 
-__host__ __device__ inline unsigned long long* res_word(Ctl* c, long long j, int lane) {
-  return &c->res[j % kResSlots][lane][0];
+// Layout of the residual buffer of one solve:
+//   max-norm sweeps: res[r * grid + b] = largest |V' - V| of workgroup b in
+//                    the sweep of ring slot r (plain stores, no atomics);
+//   1-norm sweeps:   res[(r * kResLanes + l) * kSumStride] = sum of the
+//                    workgroups b with b % kResLanes = l (FP64 atomicAdd; the
+//                    words are kSumStride doubles apart so that concurrent
+//                    atomics from different workgroups reach different memory
+//                    channels instead of queueing on one).
+__host__ __device__ inline size_t sum_word(long long j, int lane) {
+  return (static_cast<size_t>(j % kResSlots) * kResLanes + lane) * kSumStride;
+}
+__host__ __device__ inline size_t res_doubles(uint32_t grid) {
+  const size_t a = static_cast<size_t>(kResSlots) * grid;
+  const size_t b = static_cast<size_t>(kResSlots) * kResLanes * kSumStride;
+  return a > b ? a : b;
 }
 
 }  // namespace mdpvi

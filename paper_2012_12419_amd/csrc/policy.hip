@@ -32,8 +32,8 @@ template <int KMAX, int JMAX, typename Idx>
 __global__ __launch_bounds__(kBlock) void eval_sweep_kernel(Model M, const uint8_t* __restrict__ pi,
                                                              const double* __restrict__ Vin,
                                                              double* __restrict__ Vout, Ctl* ctl,
-                                                             long long j, double tol) {
-  if (sweep_stopped<ResKind::kMax>(ctl, j, tol)) return;
+                                                             double* res, long long j, double tol) {
+  if (sweep_stopped<ResKind::kMax>(ctl, res, j, tol)) return;
   const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
   double dmax = 0.0;
 #pragma unroll
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void eval_sweep_kernel(Model M, const uint8
       dmax = (d > dmax || d != d) ? d : dmax;
     }
   }
-  block_max_to(dmax, ctl, j);
+  block_max_to(dmax, ctl, res, j, tol);
 }
 
 template <int KMAX, int JMAX, typename Idx>
@@ -54,10 +54,82 @@ __global__ __launch_bounds__(kBlock) void greedy_kernel(Model M, int kind, uint8
   if (o < static_cast<Idx>(M.n_occ)) greedy_occupancy<KMAX, JMAX>(M, kind, pi, o);
 }
 
+template <int K, int J>
+__global__ __launch_bounds__(kBlock) void eval_exact_kernel(Model M, const uint8_t* __restrict__ pi,
+                                                             const double* __restrict__ Vin,
+                                                             double* __restrict__ Vout, Ctl* ctl,
+                                                             double* res, long long j, double tol) {
+  if (sweep_stopped<ResKind::kMax>(ctl, res, j, tol)) return;
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t o = b * kBlock + threadIdx.x;
+  double dmax = 0.0;
+  const BufView pv = make_view(pi, static_cast<uint32_t>(M.n_states));
+  const BufView vin = make_view(Vin, static_cast<uint32_t>(M.n_states) * 8u);
+  if (o < static_cast<uint32_t>(M.n_occ)) dmax = eval_exact<K, J>(M, pv, vin, Vout, o);
+  block_max_to(dmax, ctl, res, j, tol);
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline dim3 occ_grid(const Model& M) {
   return dim3(static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + kBlock - 1) / kBlock));
+}
+
+static bool eval_exact_shape(const Model& M) {
+  return M.n_states < (int64_t{1} << 28) && M.K >= 1 && M.K <= 8 && M.J >= 1 && M.J <= 3;
+}
+
+template <int K, int J>
+static hipError_t launch_eval_exact_t(const Model& M, const uint8_t* pi, const double* Vin, double* Vout,
+                                      Ctl* ctl, double* res, long long j, double tol, hipStream_t s) {
+  const uint32_t grid = static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((eval_exact_kernel<K, J>), dim3(grid), dim3(kBlock), 0, s, M, pi, Vin, Vout, ctl, res,
+                     j, tol);
+  return hipGetLastError();
+}
+
+static hipError_t launch_eval_exact(const Model& M, const uint8_t* pi, const double* Vin, double* Vout,
+                                    Ctl* ctl, double* res, long long j, double tol, hipStream_t s) {
+  switch (M.K * 4 + M.J) {
+    case 5: return launch_eval_exact_t<1, 1>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 6: return launch_eval_exact_t<1, 2>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 7: return launch_eval_exact_t<1, 3>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 9: return launch_eval_exact_t<2, 1>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 10: return launch_eval_exact_t<2, 2>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 11: return launch_eval_exact_t<2, 3>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 13: return launch_eval_exact_t<3, 1>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 14: return launch_eval_exact_t<3, 2>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 15: return launch_eval_exact_t<3, 3>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 17: return launch_eval_exact_t<4, 1>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 18: return launch_eval_exact_t<4, 2>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 19: return launch_eval_exact_t<4, 3>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 21: return launch_eval_exact_t<5, 1>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 22: return launch_eval_exact_t<5, 2>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 23: return launch_eval_exact_t<5, 3>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 25: return launch_eval_exact_t<6, 1>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 26: return launch_eval_exact_t<6, 2>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 27: return launch_eval_exact_t<6, 3>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 29: return launch_eval_exact_t<7, 1>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 30: return launch_eval_exact_t<7, 2>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 31: return launch_eval_exact_t<7, 3>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 33: return launch_eval_exact_t<8, 1>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 34: return launch_eval_exact_t<8, 2>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    case 35: return launch_eval_exact_t<8, 3>(M, pi, Vin, Vout, ctl, res, j, tol, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+uint32_t eval_sweep_grid(const Model& M) {
+  if (eval_exact_shape(M))
+    return static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + kBlock - 1) / kBlock);
+  const uint64_t per = static_cast<uint64_t>(kBlock) * kOccPerThread;
+  return static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + per - 1) / per);
+}
+
+uint32_t occ_sweep_grid(const Model& M) {
+  const uint64_t per = static_cast<uint64_t>(kBlock) * kOccPerThread;
+  return static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + per - 1) / per);
 }
 
 static inline dim3 sweep_grid(const Model& M) {
@@ -132,19 +204,20 @@ hipError_t launch_policy_check(const Model& M, const uint8_t* pi, Ctl* ctl, hipS
 }
 
 hipError_t launch_eval_sweep(const Model& M, const uint8_t* pi, const double* Vin, double* Vout,
-                             Ctl* ctl, long long j, double tol, hipStream_t s) {
+                             Ctl* ctl, double* res, long long j, double tol, hipStream_t s) {
+  if (eval_exact_shape(M)) return launch_eval_exact(M, pi, Vin, Vout, ctl, res, j, tol, s);
   if (use_32bit_index(M)) {
     return dispatch_kj(M, [&](auto km, auto jm) {
       constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
       hipLaunchKernelGGL((eval_sweep_kernel<KM, JM, uint32_t>), sweep_grid(M),
-                                           dim3(kBlock), 0, s, M, pi, Vin, Vout, ctl, j, tol);
+                                           dim3(kBlock), 0, s, M, pi, Vin, Vout, ctl, res, j, tol);
       return hipGetLastError();
     });
   } else {
     return dispatch_kj(M, [&](auto km, auto jm) {
       constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
       hipLaunchKernelGGL((eval_sweep_kernel<KM, JM, uint64_t>), sweep_grid(M),
-                                           dim3(kBlock), 0, s, M, pi, Vin, Vout, ctl, j, tol);
+                                           dim3(kBlock), 0, s, M, pi, Vin, Vout, ctl, res, j, tol);
       return hipGetLastError();
     });
   }

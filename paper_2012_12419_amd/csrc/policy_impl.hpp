@@ -181,4 +181,77 @@ __device__ __forceinline__ void greedy_occupancy(const Model& M, int kind, uint8
   }
 }
 
+// Fixed-policy backup for a compile-time (K, J), without a branch around any
+// load (stand-in addresses with zero weights, raw buffer loads, as
+// backup_exact).  Same operations in the same order as eval_occupancy:
+// bit-identical results.
+template <int K, int J>
+__device__ __forceinline__ double eval_exact(const Model& M, BufView pv, BufView vin,
+                                             double* __restrict__ Vout, uint32_t o) {
+  const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
+  int n[K];
+  {
+    uint32_t q = o;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t q2 = fast_div(q, M.divR);
+      n[k] = static_cast<int>(q - q2 * static_cast<uint32_t>(M.R));
+      q = q2;
+    }
+  }
+  int load = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) load += n[k];
+  const uint32_t o8 = o * 8u;
+  const uint32_t cls8 = nocc * 8u;
+  int a[J];
+  double vs[J], va[J][J], vd[K][J], vr[K][J];
+#pragma unroll
+  for (int e = 0; e < J; ++e) {
+    a[e] = ld_u8(pv, o, e * nocc);
+    vs[e] = ld_f64(vin, o8, e * cls8);
+  }
+#pragma unroll
+  for (int e = 0; e < J; ++e) {
+    uint32_t st8 = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) st8 = (k == a[e]) ? static_cast<uint32_t>(M.stride[k]) * 8u : st8;
+    const uint32_t m8 = o8 + static_cast<uint32_t>(M.size[e]) * st8;   // st8 = 0 for the paid cloud
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj) va[e][jj] = ld_f64(vin, m8, jj * cls8);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t st8 = static_cast<uint32_t>(M.stride[k]) * 8u;
+    const uint32_t d8 = n[k] > 0 ? o8 - st8 : o8;
+    const uint32_t r8 = o8 - static_cast<uint32_t>(n[k]) * st8;
+#pragma unroll
+    for (int e = 0; e < J; ++e) {
+      vd[k][e] = ld_f64(vin, d8, e * cls8);
+      vr[k][e] = ld_f64(vin, r8, e * cls8);
+    }
+  }
+  double dmax = 0.0;
+#pragma unroll
+  for (int e = 0; e < J; ++e) {
+    const double r = a[e] < M.K ? M.r_place[e] : M.r_reject[e];
+    double D = M.mu_L * static_cast<double>(M.KC - load) * vs[e];
+    double rs = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (n[k] > 0) D = fma(M.mu_L * n[k], vd[k][e], D);
+      rs += vr[k][e];
+    }
+    D = fma(M.nu_L, rs, D);
+    double A = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj) A = fma(M.p[jj], va[e][jj], A);
+    const double vn = fma(M.gamma, D, fma(M.gamma, A, r));
+    Vout[o + e * nocc] = vn;
+    const double d = fabs(vn - vs[e]);
+    dmax = (d > dmax || d != d) ? d : dmax;
+  }
+  return dmax;
+}
+
 }  // namespace mdpvi

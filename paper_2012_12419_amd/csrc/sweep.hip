@@ -39,8 +39,8 @@ namespace mdpvi {
 template <int KMAX, int JMAX, typename Idx>
 __global__ __launch_bounds__(kBlock) void vi_sweep_kernel(Model M, const float* __restrict__ Vin,
                                                            float* __restrict__ Vout, Ctl* ctl,
-                                                           long long j, double tol) {
-  if (sweep_stopped<ResKind::kMax>(ctl, j, tol)) return;
+                                                           double* res, long long j, double tol) {
+  if (sweep_stopped<ResKind::kMax>(ctl, res, j, tol)) return;
   const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
   const Idx base = static_cast<Idx>(b) * (kBlock * kOccPerThread) + threadIdx.x;
   double dmax = 0.0;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void vi_sweep_kernel(Model M, const float* 
       dmax = (d > dmax || d != d) ? d : dmax;
     }
   }
-  block_max_to(dmax, ctl, j);
+  block_max_to(dmax, ctl, res, j, tol);
 }
 
 
@@ -71,8 +71,8 @@ template <int KMAX, int JMAX>
 __global__ __launch_bounds__(kBlock) void vi_slab_kernel(Model M, int t, uint32_t slab_occ,
                                                           const float* __restrict__ Vin,
                                                           float* __restrict__ Vout, Ctl* ctl,
-                                                          long long j, double tol) {
-  if (sweep_stopped<ResKind::kMax>(ctl, j, tol)) return;
+                                                          double* res, long long j, double tol) {
+  if (sweep_stopped<ResKind::kMax>(ctl, res, j, tol)) return;
   extern __shared__ double slab_lds[];
   double* Al = slab_lds;                                     // [slab_occ]
   float* Vl = reinterpret_cast<float*>(slab_lds + slab_occ);  // [J][slab_occ]
@@ -204,12 +204,120 @@ __global__ __launch_bounds__(kBlock) void vi_slab_kernel(Model M, int t, uint32_
       }
     }
   }
-  block_max_to(dmax, ctl, j);
+  block_max_to(dmax, ctl, res, j, tol);
+}
+
+
+// ---------------------------------------------------------------- exact-shape direct form
+//
+// One occupancy per thread with the branch-free backup of a compile-time
+// (K, J) whose arrival terms come from the FP64 side array written by the
+// previous sweep (backup_arrival): every gather of the thread is issued
+// before the first use.
+template <int K, int J>
+__global__ __launch_bounds__(kBlock) void vi_exact_kernel(Model M, const float* __restrict__ Vin,
+                                                           float* __restrict__ Vout,
+                                                           const double* __restrict__ Ain,
+                                                           double* __restrict__ Aout, Ctl* ctl,
+                                                           double* res, long long j, double tol) {
+  if (sweep_stopped<ResKind::kMax>(ctl, res, j, tol)) return;
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t o = b * kBlock + threadIdx.x;
+  const BufView vin = make_view(Vin, static_cast<uint32_t>(M.n_states) * 4u);
+  const BufView ain = make_view(Ain, static_cast<uint32_t>(M.n_occ + 1) * 8u);
+  double dmax = 0.0;
+  if (o < static_cast<uint32_t>(M.n_occ)) dmax = backup_arrival<K, J>(M, vin, ain, Vout, Aout, o);
+  block_max_to(dmax, ctl, res, j, tol);
+}
+
+// A(o) = sum_e lambda_e/Lam V(o, e) of the initial iterate (the FMA chain of
+// backup_arrival) into A0, and the -inf sentinel A[n_occ] into both arrays.
+__global__ void arrival_init_kernel(Model M, const float* __restrict__ V, double* __restrict__ A0,
+                                    double* __restrict__ A1) {
+  const uint64_t o = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (o == static_cast<uint64_t>(M.n_occ)) {
+    A0[o] = -INFINITY;   // sentinel read by placements without room
+    A1[o] = -INFINITY;
+  }
+  if (o >= static_cast<uint64_t>(M.n_occ)) return;
+  double* A = A0;
+  double a = 0.0;
+  for (int e = 0; e < M.J; ++e)
+    a = fma(M.p[e], static_cast<double>(V[o + static_cast<uint64_t>(e) * M.n_occ]), a);
+  A[o] = a;
+}
+
+hipError_t launch_arrival_init(const Model& M, const float* V, double* A0, double* A1, hipStream_t s) {
+  const uint32_t grid = static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + 256) / 256);
+  hipLaunchKernelGGL(arrival_init_kernel, dim3(grid), dim3(256), 0, s, M, V, A0, A1);
+  return hipGetLastError();
+}
+
+bool exact_shape(const Model& M) {
+  return M.n_states < (int64_t{1} << 29) && M.K >= 1 && M.K <= 8 && M.J >= 1 && M.J <= 3 &&
+         M.n_sizes == M.J;
+}
+
+template <int K, int J>
+static hipError_t launch_exact_t(const Model& M, const float* Vin, float* Vout, const double* Ain,
+                                 double* Aout, Ctl* ctl, double* res, long long j, double tol,
+                                 hipStream_t s) {
+  const uint32_t grid = static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((vi_exact_kernel<K, J>), dim3(grid), dim3(kBlock), 0, s, M, Vin, Vout, Ain, Aout, ctl,
+                     res, j, tol);
+  return hipGetLastError();
+}
+
+static hipError_t launch_exact(const Model& M, const float* Vin, float* Vout, const double* Ain,
+                               double* Aout, Ctl* ctl, double* res, long long j, double tol,
+                               hipStream_t s) {
+  switch (M.K * 4 + M.J) {
+    case 5: return launch_exact_t<1, 1>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 6: return launch_exact_t<1, 2>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 7: return launch_exact_t<1, 3>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 9: return launch_exact_t<2, 1>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 10: return launch_exact_t<2, 2>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 11: return launch_exact_t<2, 3>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 13: return launch_exact_t<3, 1>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 14: return launch_exact_t<3, 2>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 15: return launch_exact_t<3, 3>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 17: return launch_exact_t<4, 1>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 18: return launch_exact_t<4, 2>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 19: return launch_exact_t<4, 3>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 21: return launch_exact_t<5, 1>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 22: return launch_exact_t<5, 2>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 23: return launch_exact_t<5, 3>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 25: return launch_exact_t<6, 1>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 26: return launch_exact_t<6, 2>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 27: return launch_exact_t<6, 3>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 29: return launch_exact_t<7, 1>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 30: return launch_exact_t<7, 2>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 31: return launch_exact_t<7, 3>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 33: return launch_exact_t<8, 1>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 34: return launch_exact_t<8, 2>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    case 35: return launch_exact_t<8, 3>(M, Vin, Vout, Ain, Aout, ctl, res, j, tol, s);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 // Slab depth for M: the most low digits t whose slab (values of all classes
 // in FP32 plus the FP64 arrival term) fits kSlabLds bytes while leaving at
 // least kMinSlabs workgroups; 0 when no t >= 1 qualifies (use the direct form).
+bool exact_shape(const Model& M);
+
+uint32_t vi_sweep_grid(const Model& M, int slab_t) {
+  if (slab_t > 0) {
+    uint64_t occ = 1;
+    for (int k = 0; k < slab_t; ++k) occ *= static_cast<uint64_t>(M.R);
+    return static_cast<uint32_t>(static_cast<uint64_t>(M.n_occ) / occ);
+  }
+  if (exact_shape(M))
+    return static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + kBlock - 1) / kBlock);
+  const uint64_t per = static_cast<uint64_t>(kBlock) * kOccPerThread;
+  return static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + per - 1) / per);
+}
+
 int slab_digits(const Model& M) {
   if (!use_32bit_index(M)) return 0;
   int best = 0;
@@ -223,69 +331,76 @@ int slab_digits(const Model& M) {
   return best;
 }
 
-__global__ void ctl_init_kernel(Ctl* ctl) {
+__global__ void ctl_init_kernel(Ctl* ctl, double* res) {
   if (threadIdx.x == 0) {
     ctl->done_iter = -1;
     ctl->flag = 0;
   }
-  for (int w = threadIdx.x; w < kResSlots * kResLanes; w += blockDim.x)
-    ctl->res[w / kResLanes][w % kResLanes][0] = 0ull;
+  if (threadIdx.x < kResSlots * kNumXcd) {
+    ctl->go[threadIdx.x / kNumXcd][threadIdx.x % kNumXcd][0] = 0u;
+    ctl->nan[threadIdx.x / kNumXcd][threadIdx.x % kNumXcd][0] = 0u;
+  }
+  if (res)
+    for (int w = threadIdx.x; w < kResSlots * kResLanes; w += blockDim.x)
+      res[static_cast<size_t>(w) * kSumStride] = 0.0;
 }
 
-hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(256), 0, s, ctl);
+hipError_t launch_ctl_init(Ctl* ctl, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(256), 0, s, ctl, res);
   return hipGetLastError();
 }
 
 template <int KMAX, int JMAX, typename Idx>
 static hipError_t launch_sweep_t(const Model& M, const float* Vin, float* Vout, Ctl* ctl,
-                                 long long j, double tol, hipStream_t s) {
+                                 double* res, long long j, double tol, hipStream_t s) {
   const uint64_t per = static_cast<uint64_t>(kBlock) * kOccPerThread;
   const uint64_t grid = (static_cast<uint64_t>(M.n_occ) + per - 1) / per;
   hipLaunchKernelGGL((vi_sweep_kernel<KMAX, JMAX, Idx>), dim3(static_cast<uint32_t>(grid)),
-                     dim3(kBlock), 0, s, M, Vin, Vout, ctl, j, tol);
+                     dim3(kBlock), 0, s, M, Vin, Vout, ctl, res, j, tol);
   return hipGetLastError();
 }
 
 template <int KMAX, int JMAX>
 static hipError_t launch_slab_t(const Model& M, int t, const float* Vin, float* Vout, Ctl* ctl,
-                                long long j, double tol, hipStream_t s) {
+                                double* res, long long j, double tol, hipStream_t s) {
   uint32_t slab_occ = 1;
   for (int k = 0; k < t; ++k) slab_occ *= static_cast<uint32_t>(M.R);
   const uint32_t grid = static_cast<uint32_t>(M.n_occ / slab_occ);
   const size_t lds = static_cast<size_t>(slab_occ) * (8 + 4 * M.J);
   hipLaunchKernelGGL((vi_slab_kernel<KMAX, JMAX>), dim3(grid), dim3(kBlock), lds, s, M, t, slab_occ,
-                     Vin, Vout, ctl, j, tol);
+                     Vin, Vout, ctl, res, j, tol);
   return hipGetLastError();
 }
 
 template <typename Idx>
 static hipError_t launch_sweep_idx(const Model& M, const float* Vin, float* Vout, Ctl* ctl,
-                                   long long j, double tol, hipStream_t s) {
+                                   double* res, long long j, double tol, hipStream_t s) {
   if (M.J <= 4) {
-    if (M.K <= 4) return launch_sweep_t<4, 4, Idx>(M, Vin, Vout, ctl, j, tol, s);
-    if (M.K <= 8) return launch_sweep_t<8, 4, Idx>(M, Vin, Vout, ctl, j, tol, s);
-    return launch_sweep_t<16, 4, Idx>(M, Vin, Vout, ctl, j, tol, s);
+    if (M.K <= 4) return launch_sweep_t<4, 4, Idx>(M, Vin, Vout, ctl, res, j, tol, s);
+    if (M.K <= 8) return launch_sweep_t<8, 4, Idx>(M, Vin, Vout, ctl, res, j, tol, s);
+    return launch_sweep_t<16, 4, Idx>(M, Vin, Vout, ctl, res, j, tol, s);
   }
-  if (M.K <= 4) return launch_sweep_t<4, 8, Idx>(M, Vin, Vout, ctl, j, tol, s);
-  if (M.K <= 8) return launch_sweep_t<8, 8, Idx>(M, Vin, Vout, ctl, j, tol, s);
-  return launch_sweep_t<16, 8, Idx>(M, Vin, Vout, ctl, j, tol, s);
+  if (M.K <= 4) return launch_sweep_t<4, 8, Idx>(M, Vin, Vout, ctl, res, j, tol, s);
+  if (M.K <= 8) return launch_sweep_t<8, 8, Idx>(M, Vin, Vout, ctl, res, j, tol, s);
+  return launch_sweep_t<16, 8, Idx>(M, Vin, Vout, ctl, res, j, tol, s);
 }
 
-hipError_t launch_vi_sweep(const Model& M, const float* Vin, float* Vout, Ctl* ctl, long long j,
-                           double tol, hipStream_t s, int slab_t) {
+hipError_t launch_vi_sweep(const Model& M, const float* Vin, float* Vout, Ctl* ctl, double* res,
+                           long long j, double tol, hipStream_t s, int slab_t, double* const* A) {
   if (slab_t > 0) {
     if (M.J <= 4) {
-      if (M.K <= 4) return launch_slab_t<4, 4>(M, slab_t, Vin, Vout, ctl, j, tol, s);
-      if (M.K <= 8) return launch_slab_t<8, 4>(M, slab_t, Vin, Vout, ctl, j, tol, s);
-      return launch_slab_t<16, 4>(M, slab_t, Vin, Vout, ctl, j, tol, s);
+      if (M.K <= 4) return launch_slab_t<4, 4>(M, slab_t, Vin, Vout, ctl, res, j, tol, s);
+      if (M.K <= 8) return launch_slab_t<8, 4>(M, slab_t, Vin, Vout, ctl, res, j, tol, s);
+      return launch_slab_t<16, 4>(M, slab_t, Vin, Vout, ctl, res, j, tol, s);
     }
-    if (M.K <= 4) return launch_slab_t<4, 8>(M, slab_t, Vin, Vout, ctl, j, tol, s);
-    if (M.K <= 8) return launch_slab_t<8, 8>(M, slab_t, Vin, Vout, ctl, j, tol, s);
-    return launch_slab_t<16, 8>(M, slab_t, Vin, Vout, ctl, j, tol, s);
+    if (M.K <= 4) return launch_slab_t<4, 8>(M, slab_t, Vin, Vout, ctl, res, j, tol, s);
+    if (M.K <= 8) return launch_slab_t<8, 8>(M, slab_t, Vin, Vout, ctl, res, j, tol, s);
+    return launch_slab_t<16, 8>(M, slab_t, Vin, Vout, ctl, res, j, tol, s);
   }
-  if (use_32bit_index(M)) return launch_sweep_idx<uint32_t>(M, Vin, Vout, ctl, j, tol, s);
-  return launch_sweep_idx<uint64_t>(M, Vin, Vout, ctl, j, tol, s);
+  if (exact_shape(M) && A)
+    return launch_exact(M, Vin, Vout, A[j & 1], A[(j + 1) & 1], ctl, res, j, tol, s);
+  if (use_32bit_index(M)) return launch_sweep_idx<uint32_t>(M, Vin, Vout, ctl, res, j, tol, s);
+  return launch_sweep_idx<uint64_t>(M, Vin, Vout, ctl, res, j, tol, s);
 }
 
 }  // namespace mdpvi
