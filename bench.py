@@ -53,6 +53,59 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def batched_vs_per_instance(mdpvi, n: int, tol: float) -> dict:
+    """The 512-instance parameter sweep solved by one vi_solve_batch call and
+    by one vi_solve call per instance on the same stream (handles built and
+    value arrays allocated outside the timed regions)."""
+    import torch
+
+    import workloads as W
+    insts = W.batch(n, seed=3)
+    b = mdpvi.Batch(insts)
+    V = torch.zeros(b.num_states, device="cuda")
+    b.vi_solve(V, tol=tol)                     # warm-up (first-use allocations)
+    V.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, its, _ = b.vi_solve(V, tol=tol)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    mdps = [mdpvi.MDP.from_instance(p) for p in insts]
+    Vs = [torch.zeros(m.num_states, device="cuda") for m in mdps]
+    for m, v in zip(mdps[:8], Vs[:8]):
+        m.vi_solve(v, tol=tol)
+        v.zero_()
+    torch.cuda.synchronize()
+    backups_single = 0.0
+    t0 = time.perf_counter()
+    for m, v in zip(mdps, Vs):
+        backups_single += m.vi_solve(v, tol=tol)["backups"]
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    return {"instances": n, "states": b.num_states, "tol": tol,
+            "batched_seconds": t_batch, "batched_backups_per_s": st["backups"] / t_batch,
+            "per_instance_seconds": t_single, "per_instance_backups_per_s": backups_single / t_single,
+            "speedup": t_single / t_batch, "max_sweeps": max(its)}
+
+
+def traffic_record(kernel_files, name: str):
+    """HBM traffic of a kernel from the committed counter record, or None when
+    the record is missing or its sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for fn in kernel_files:
+        with open(os.path.join(ROOT, fn), "rb") as f:
+            h.update(f.read())
+    if rec.get("source_sha256") != h.hexdigest():
+        return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(inst, sweeps: int) -> dict:
     """The FP64 NumPy oracle's Jacobi sweep, single-threaded, on `sweeps`
     sweeps from V = 0 of the same instance."""
@@ -87,6 +140,8 @@ def main() -> int:
                     help="do not bracket sweeps with events (roofline fields become null)")
     ap.add_argument("--sweep-form", type=int, default=-1,
                     help="value-iteration sweep kernel: -1 automatic, 0 direct, t>0 LDS slab of t digits")
+    ap.add_argument("--batch", type=int, default=512,
+                    help="instances of the batched-vs-per-instance comparison (0: skip)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -172,10 +227,16 @@ def main() -> int:
             kernels[name] = {"launches": cnt, "avg_us": avg * 1e6, "bytes_per_launch": bps * N,
                              "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
                              "share_of_step": tot / elapsed}
+        srcs = {"vi_sweep_kernel": ["paper_2012_12419_amd/csrc/sweep.hip",
+                                    "paper_2012_12419_amd/csrc/sweep_impl.hpp"],
+                "eval_sweep_kernel": ["paper_2012_12419_amd/csrc/policy.hip",
+                                      "paper_2012_12419_amd/csrc/policy_impl.hpp"]}
+        for name in kernels:
+            kernels[name]["traffic"] = traffic_record(srcs[name], f"{name}_{args.workload}")
         dom = max(kernels, key=lambda k: kernels[k]["share_of_step"])
         kd = kernels[dom]
         roof = {"bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": kd["frac"], "traffic": None, "kernel": dom}
+                "unit": "GB/s", "frac": kd["frac"], "traffic": kd["traffic"], "kernel": dom}
 
     Vh = V.double()
     J_opt = float((c.to(dev) * Vp[empty]).sum())
@@ -211,6 +272,8 @@ def main() -> int:
         "kernels": kernels,
     }
     del Vh
+    if args.batch:
+        out["batched_vs_per_instance"] = batched_vs_per_instance(mdpvi, args.batch, args.tol)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps)
     print(json.dumps(out), flush=True)
