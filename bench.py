@@ -19,9 +19,10 @@ value = state-action backups per second over the timed steps: feasible
 backup per state per fixed-policy sweep, divided by the wall time of the
 steps.  The JSON line also carries the time to ||dV||_inf < 1e-6, the
 roofline of the dominant kernel (algorithmic bytes per launch over the
-average launch duration, both kernels' durations measured with HIP events
-bracketing every sweep on its stream) and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+average launch duration; the durations come from one extra step, outside
+the timed ones, in which HIP events bracket every sweep on the solver's
+stream) and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -137,9 +138,10 @@ def main() -> int:
     ap.add_argument("--cpu-sweeps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
-                    help="do not bracket sweeps with events (roofline fields become null)")
+                    help="skip the extra event-bracketed step (roofline fields become null)")
     ap.add_argument("--sweep-form", type=int, default=-1,
-                    help="value-iteration sweep kernel: -1 automatic, 0 direct, t>0 LDS slab of t digits")
+                    help="sweep kernels: -1 automatic, 0 direct, t in 1..K-1 LDS slab of t digits, "
+                         "16+w tile form (w workgroups per CU, 0: one per tile)")
     ap.add_argument("--batch", type=int, default=512,
                     help="instances of the batched-vs-per-instance comparison (0: skip)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -163,8 +165,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     inst, desc = workload(args.workload)
     mdp = mdpvi.MDP.from_instance(inst)
-    mdp.set_timing(not args.no_timing)
     mdp.set_sweep_form(args.sweep_form)
+    vi_form, ev_form = mdp.sweep_forms()
     N = mdp.num_states
     dev = "cuda:0"
     V = torch.zeros(N, dtype=torch.float32, device=dev)
@@ -200,6 +202,15 @@ def main() -> int:
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
+    # one more step with every sweep bracketed by HIP events on the solver's
+    # stream (outside the timed region): per-kernel durations
+    meas = None
+    if not args.no_timing:
+        mdp.set_timing(True)
+        meas = step()
+        torch.cuda.synchronize()
+        mdp.set_timing(False)
+
     if args.copy_calibration_mb:
         n = args.copy_calibration_mb * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)
@@ -215,28 +226,37 @@ def main() -> int:
 
     roof = None
     kernels = {}
-    if not args.no_timing:
-        vi_k = sum(r[0]["sweep_seconds"] for r in recs)
-        ev_k = sum(r[1]["sweep_seconds"] + r[2]["sweep_seconds"] for r in recs)
-        n_vi = sum(vi_sweeps)
-        n_ev = sum(ev_sweeps) + sum(g_sweeps)
-        for name, tot, cnt, bps in [("vi_sweep_kernel", vi_k, n_vi, VI_BYTES_PER_STATE),
-                                    ("eval_sweep_kernel", ev_k, n_ev, EVAL_BYTES_PER_STATE)]:
+    if meas is not None:
+        tile = 16
+        vi_impl = ("vi_tile_kernel" if vi_form >= tile else
+                   "vi_slab_kernel" if vi_form > 0 else "vi_exact_kernel")
+        ev_impl = "eval_tile_kernel" if ev_form >= tile else "eval_exact_kernel"
+        srcs = {"vi_tile_kernel": ["paper_2012_12419_amd/csrc/tile_vi.hip", "paper_2012_12419_amd/csrc/tile.hpp"],
+                "vi_exact_kernel": ["paper_2012_12419_amd/csrc/sweep.hip",
+                                    "paper_2012_12419_amd/csrc/sweep_impl.hpp"],
+                "vi_slab_kernel": ["paper_2012_12419_amd/csrc/sweep.hip",
+                                   "paper_2012_12419_amd/csrc/sweep_impl.hpp"],
+                "eval_tile_kernel": ["paper_2012_12419_amd/csrc/tile_eval.hip",
+                                     "paper_2012_12419_amd/csrc/tile.hpp"],
+                "eval_exact_kernel": ["paper_2012_12419_amd/csrc/policy.hip",
+                                      "paper_2012_12419_amd/csrc/policy_impl.hpp"]}
+        n_vi = meas[0]["iterations"]
+        n_ev = meas[1]["iterations"] + meas[2]["iterations"]
+        t_meas = meas[0]["seconds"] + meas[1]["seconds"] + meas[2]["seconds"]
+        for name, impl, tot, cnt, bps in [
+                ("vi_sweep_kernel", vi_impl, meas[0]["sweep_seconds"], n_vi, VI_BYTES_PER_STATE),
+                ("eval_sweep_kernel", ev_impl, meas[1]["sweep_seconds"] + meas[2]["sweep_seconds"], n_ev,
+                 EVAL_BYTES_PER_STATE)]:
             avg = tot / cnt
             ach = bps * N / avg / 1e9
-            kernels[name] = {"launches": cnt, "avg_us": avg * 1e6, "bytes_per_launch": bps * N,
+            kernels[name] = {"kernel": impl, "launches": cnt, "avg_us": avg * 1e6, "bytes_per_launch": bps * N,
                              "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
-                             "share_of_step": tot / elapsed}
-        srcs = {"vi_sweep_kernel": ["paper_2012_12419_amd/csrc/sweep.hip",
-                                    "paper_2012_12419_amd/csrc/sweep_impl.hpp"],
-                "eval_sweep_kernel": ["paper_2012_12419_amd/csrc/policy.hip",
-                                      "paper_2012_12419_amd/csrc/policy_impl.hpp"]}
-        for name in kernels:
-            kernels[name]["traffic"] = traffic_record(srcs[name], f"{name}_{args.workload}")
-        dom = max(kernels, key=lambda k: kernels[k]["share_of_step"])
+                             "share_of_solve_time": tot / t_meas,
+                             "traffic": traffic_record(srcs[impl], f"{impl}_{args.workload}")}
+        dom = max(kernels, key=lambda k: kernels[k]["share_of_solve_time"])
         kd = kernels[dom]
         roof = {"bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": kd["frac"], "traffic": kd["traffic"], "kernel": dom}
+                "unit": "GB/s", "frac": kd["frac"], "traffic": kd["traffic"], "kernel": kd["kernel"]}
 
     Vh = V.double()
     J_opt = float((c.to(dev) * Vp[empty]).sum())
@@ -259,6 +279,7 @@ def main() -> int:
         "config": {"workload": f"{args.workload}: {desc}", "states": N,
                    "feasible_pairs_per_sweep": mdp.feasible_pairs, "tol": args.tol,
                    "eval_tol": args.eval_tol, "sweep_form": args.sweep_form,
+                   "forms_in_use": {"vi": vi_form, "eval": ev_form},
                    "values": "FP32 storage, FP64 sums (VI); FP64 (evaluation)"},
         "time_to_tol_s": t_tol,
         "vi_sweeps": vi_sweeps,

@@ -59,6 +59,7 @@ extern "C" {
 
 #define MDPVI_MAX_K 16       /* hosts */
 #define MDPVI_MAX_J 8        /* task classes */
+#define MDPVI_FORM_TILE 16   /* mdp_set_sweep_form: the tile form */
 
 /* Model parameters (Sec. V-B..V-E).  All pointers are host pointers to J
  * entries, read during mdp_build only.
@@ -216,12 +217,22 @@ int vi_solve_batch(mdpvi_batch_t b, float *V, double tol, int64_t max_iter,
                    void *hip_stream, mdpvi_stats *st, int64_t *iterations,
                    double *residuals);
 
-/* Choice of the value-iteration sweep kernel for this handle (a tuning knob;
- * every form computes bit-identical iterates).  slab_digits = -1: automatic
- * (the default); 0: the direct form (every neighbour read from global
- * memory); t > 0: the LDS slab form, each workgroup staging the (C+1)^t
- * occupancies that share the high digits.  Errors: MDPVI_EINVAL (NULL
- * handle, t >= K, or a slab that does not fit 64 KB of LDS).                */
+/* Choice of the sweep kernels for this handle (a tuning knob; every form
+ * computes bit-identical iterates).  slab_digits = -1: automatic (the
+ * default); 0: the direct forms (every neighbour read from global memory);
+ * t in 1..K-1: the LDS slab form of value iteration, each workgroup staging
+ * the (C+1)^t occupancies that share the high digits (evaluation: direct);
+ * MDPVI_FORM_TILE + w (w = 0..8): the tile form of value iteration and
+ * evaluation, the exact-shape counterpart of the slab form (K in 3..8,
+ * J <= 3 distinct sizes, (C+1)^T occupancies per tile for the deepest T in
+ * 2..4 whose tile fits 48 KB of LDS); w = 0 launches one workgroup per
+ * tile, w > 0 launches w workgroups per CU that walk their XCD's tiles in
+ * order.  The automatic choice requires at least 256 occupancies per tile
+ * and 256 tiles.
+ * Automatic mode uses the tile form where it applies, unless mdp_autotune
+ * recorded another form for the shape, then the exact-shape direct form,
+ * then the slab form.  Errors: MDPVI_EINVAL (NULL handle, t >= K, a slab
+ * that does not fit 64 KB of LDS, or a tile form that does not apply).     */
 int mdp_set_sweep_form(mdpvi_mdp_t h, int32_t slab_digits);
 
 /* Batched extraction / greedy heuristic: as policy_extract(_f64) and
@@ -250,8 +261,14 @@ int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t *pi, const double *V_pi, flo
                      double *grad, double *objective, double tol, int64_t max_iter,
                      void *hip_stream, mdpvi_stats *st, int64_t *iterations);
 
-/* Autotuner: times every applicable sweep form (direct, and LDS slabs of
- * 1..K-1 low digits that fit 64 KB) on this instance, `trials` single sweeps
+/* The forms the next vi_solve and policy_eval on this handle run (after the
+ * automatic choice): vi, eval (host, nullable).  A value in 1..K-1 is a slab
+ * depth, 0 the direct form (the exact-shape one where it applies),
+ * MDPVI_FORM_TILE + w the tile form.  Errors: MDPVI_EINVAL (NULL handle).   */
+int mdp_sweep_forms(mdpvi_mdp_t h, int32_t *vi, int32_t *eval);
+
+/* Autotuner: times every applicable value-iteration form (direct, LDS slabs
+ * of 1..K-1 low digits that fit 64 KB, tile) on this instance, `trials` single sweeps
  * each from V (device float[N], read only; the sweeps write the handle's
  * scratch), keeps the form with the smallest median time, and records it
  * for the shape (GPU arch, K, C, J, sizes): later vi_solve calls in automatic

@@ -30,6 +30,7 @@ ENOCONV = -3
 ENAN = -4
 EDEVICE = -5
 ENOMEM = -6
+FORM_TILE = 16   # mdp_set_sweep_form: the tile form
 _NAMES = {EINVAL: "EINVAL", ERANGE: "ERANGE", ENOCONV: "ENOCONV", ENAN: "ENAN",
           EDEVICE: "EDEVICE", ENOMEM: "ENOMEM"}
 
@@ -90,6 +91,7 @@ SIGNATURES = {
                                         ctypes.POINTER(Stats), ctypes.POINTER(_c_int64)]),
     "mdp_set_timing": (ctypes.c_int, [_vp, _c_int32]),
     "mdp_set_sweep_form": (ctypes.c_int, [_vp, _c_int32]),
+    "mdp_sweep_forms": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32)]),
     "mdp_autotune": (ctypes.c_int, [_vp, _vp, _c_int32, _vp, ctypes.POINTER(_c_int32),
                                     ctypes.POINTER(_c_double)]),
     "mdpvi_last_error": (ctypes.c_char_p, []),
@@ -201,8 +203,15 @@ class MDP:
         _check(load().mdp_set_timing(self._h, 1 if on else 0))
 
     def set_sweep_form(self, slab_digits: int = -1):
-        """-1 automatic, 0 direct, t > 0 LDS slab of t low digits."""
+        """-1 automatic, 0 direct, t in 1..K-1 LDS slab of t low digits,
+        FORM_TILE the tile form (value iteration and evaluation)."""
         _check(load().mdp_set_sweep_form(self._h, int(slab_digits)))
+
+    def sweep_forms(self):
+        """(value-iteration form, evaluation form) the next solves will run."""
+        a, b = _c_int32(), _c_int32()
+        _check(load().mdp_sweep_forms(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def autotune(self, V=None, trials: int = 10, stream=None):
         """Time every sweep form on this instance; returns (best form, us per sweep)."""

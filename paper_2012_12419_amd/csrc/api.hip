@@ -24,6 +24,7 @@
 #include "../../include/mdpvi.h"
 #include "kernels.hpp"
 #include "model.hpp"
+#include "tile.hpp"
 
 using mdpvi::Ctl;
 using mdpvi::Model;
@@ -34,7 +35,8 @@ struct mdpvi_mdp {
   int device = -1;              // device of the scratch below (-1: none yet)
   void* vbuf = nullptr;         // second value buffer (ping-pong partner)
   size_t vbuf_bytes = 0;
-  double* abuf = nullptr;       // two FP64 arrival-term arrays (exact-shape direct form)
+  double* abuf = nullptr;       // two FP64 arrival-term arrays of n_occ + kSentinel doubles
+                                // (exact-shape direct and tile forms)
   Ctl* ctl = nullptr;           // device control words
   Ctl* ctl_host = nullptr;      // pinned mirror
   double* res = nullptr;        // residual words / per-workgroup partials
@@ -45,7 +47,8 @@ struct mdpvi_mdp {
   size_t aux_bytes = 0;
   double* out_host = nullptr;   // pinned, 2 * kMaxJ + 3 doubles
   bool timing = false;          // bracket every sweep with events
-  int slab_t = -1;              // sweep form: -1 automatic, 0 direct, t > 0 slab of t digits
+  int slab_t = -1;              // sweep form: -1 automatic, 0 direct, t > 0 slab of t digits,
+                                // MDPVI_FORM_TILE the tile form
   hipEvent_t* sweep_ev = nullptr;   // 2 * kMaxChunk events (created on demand)
 };
 
@@ -159,6 +162,71 @@ int ensure_aux(mdpvi_mdp* h, size_t doubles) {
     h->aux_bytes = bytes;
   }
   return MDPVI_OK;
+}
+
+int tune_lookup(const Model& M);
+
+// The two FP64 arrival-term arrays (n_occ + kSentinel doubles each),
+// allocated on first use, initialised from V: A[0] = sum_e lambda_e/Lam
+// V(., e), and the -inf sentinel block of both.
+int arrival_arrays(mdpvi_mdp* h, const float* V, hipStream_t s, double* A[2]) {
+  const Model& M = h->M;
+  const size_t per = static_cast<size_t>(M.n_occ) + mdpvi::kSentinel;
+  if (!h->abuf && hipMalloc(reinterpret_cast<void**>(&h->abuf), 2 * per * sizeof(double)) != hipSuccess) {
+    h->abuf = nullptr;
+    return fail(MDPVI_ENOMEM, "hipMalloc of the arrival-term arrays failed");
+  }
+  A[0] = h->abuf;
+  A[1] = h->abuf + per;
+  HIP_TRY(mdpvi::launch_arrival_init(M, V, A[0], A[1], s));
+  return MDPVI_OK;
+}
+
+int cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return 1;
+  return cus;
+}
+
+bool is_tile_form(int f) { return f >= MDPVI_FORM_TILE && f <= MDPVI_FORM_TILE + 8; }
+
+// Workgroups per CU of the automatic tile form (0: one workgroup per tile).
+constexpr int kTileWalkersAuto = 0;
+
+// The value-iteration form to run: the handle's choice, else the tuned one
+// for the shape, else the tile form when it applies and is worthwhile, else
+// the exact-shape direct form, else the slab form.  S is filled for the tile form.
+int vi_form(mdpvi_mdp* h, mdpvi::TileShape* S) {
+  const Model& M = h->M;
+  const int fallback = mdpvi::exact_shape(M) ? 0 : mdpvi::slab_digits(M);
+  int f = h->slab_t;
+  if (f < 0) {
+    const int cached = tune_lookup(M);
+    if (cached >= 0)
+      f = cached;
+    else if (mdpvi::vi_tile_shape(M, S) && mdpvi::tile_worthwhile(*S))
+      f = MDPVI_FORM_TILE + kTileWalkersAuto;
+    else
+      f = fallback;
+  }
+  if (is_tile_form(f)) {
+    if (!mdpvi::vi_tile_shape(M, S)) return fallback;
+    mdpvi::tile_set_walkers(S, f - MDPVI_FORM_TILE, cu_count());
+  }
+  return f;
+}
+
+// The evaluation form to run: the tile form where it applies and is
+// worthwhile (or where the handle asks for it), else the direct form (0).
+int eval_form(mdpvi_mdp* h, mdpvi::TileShape* S) {
+  const bool forced = is_tile_form(h->slab_t);
+  if (!(h->slab_t == -1 || forced) || !mdpvi::eval_tile_shape(h->M, S) || !(forced || mdpvi::tile_worthwhile(*S)))
+    return 0;
+  const int w = forced ? h->slab_t - MDPVI_FORM_TILE : kTileWalkersAuto;
+  mdpvi::tile_set_walkers(S, w, cu_count());
+  return MDPVI_FORM_TILE + w;
 }
 
 double bits_to_double(unsigned long long b) {
@@ -500,6 +568,14 @@ void mdp_free(mdpvi_mdp_t h) {
   delete h;
 }
 
+int mdp_sweep_forms(mdpvi_mdp_t h, int32_t* vi, int32_t* eval) {
+  if (!h) return fail(MDPVI_EINVAL, "NULL handle");
+  mdpvi::TileShape S{};
+  if (vi) *vi = vi_form(h, &S);
+  if (eval) *eval = eval_form(h, &S);
+  return MDPVI_OK;
+}
+
 int mdp_set_timing(mdpvi_mdp_t h, int32_t per_sweep_events) {
   if (!h) return fail(MDPVI_EINVAL, "NULL handle");
   h->timing = per_sweep_events != 0;
@@ -508,6 +584,13 @@ int mdp_set_timing(mdpvi_mdp_t h, int32_t per_sweep_events) {
 
 int mdp_set_sweep_form(mdpvi_mdp_t h, int32_t slab_digits) {
   if (!h) return fail(MDPVI_EINVAL, "NULL handle");
+  if (is_tile_form(slab_digits)) {
+    mdpvi::TileShape S{};
+    if (!mdpvi::vi_tile_shape(h->M, &S))
+      return fail(MDPVI_EINVAL, "the tile form does not apply to this instance");
+    h->slab_t = slab_digits;
+    return MDPVI_OK;
+  }
   if (slab_digits < -1 || slab_digits >= h->M.K)
     return fail(MDPVI_EINVAL, "slab_digits=%d outside [-1, K-1=%d]", slab_digits, h->M.K - 1);
   if (slab_digits > 0) {
@@ -538,29 +621,34 @@ int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream
         forms.push_back(t);
     }
   }
+  mdpvi::TileShape S{};
+  if (mdpvi::vi_tile_shape(M, &S))
+    for (int w = 0; w <= 4; ++w) forms.push_back(MDPVI_FORM_TILE + w);
   float* out = static_cast<float*>(h->vbuf);
   double* A[2] = {nullptr, nullptr};
-  if (mdpvi::exact_shape(M)) {
-    if (!h->abuf && hipMalloc(reinterpret_cast<void**>(&h->abuf), 2 * (M.n_occ + 1) * sizeof(double)) != hipSuccess) {
-      h->abuf = nullptr;
-      return fail(MDPVI_ENOMEM, "hipMalloc of the arrival-term arrays failed");
-    }
-    A[0] = h->abuf;
-    A[1] = h->abuf + M.n_occ + 1;
-    HIP_TRY(mdpvi::launch_arrival_init(M, V, A[0], A[1], s));
+  if (mdpvi::exact_shape(M) || is_tile_form(forms.back())) {
+    int arc = arrival_arrays(h, V, s, A);
+    if (arc) return arc;
   }
+  // sweep 0 (no stopping test) from V into the scratch buffer
+  auto sweep = [&](int form) -> hipError_t {
+    if (is_tile_form(form)) {
+      mdpvi::tile_set_walkers(&S, form - MDPVI_FORM_TILE, cu_count());
+      return mdpvi::launch_vi_tile(M, S, V, out, A[0], A[1], h->ctl, h->res, 0, 1.0, s);
+    }
+    return mdpvi::launch_vi_sweep(M, V, out, h->ctl, h->res, 0, 1.0, s, form,
+                                  (form == 0 && A[0] && mdpvi::exact_shape(M)) ? A : nullptr);
+  };
   int best = 0;
   double best_t = 1e300;
   for (int form : forms) {
-    double* const* Af = (form == 0 && A[0]) ? A : nullptr;
-    // sweep 0 (no stopping test) from V into the scratch buffer, untimed once
-    HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));
-    HIP_TRY(mdpvi::launch_vi_sweep(M, V, out, h->ctl, h->res, 0, 1.0, s, form, Af));
+    HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));   // untimed once
+    HIP_TRY(sweep(form));
     std::vector<float> ms(trials);
     for (int r = 0; r < trials; ++r) {
       HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));
       HIP_TRY(hipEventRecord(h->ev0, s));
-      HIP_TRY(mdpvi::launch_vi_sweep(M, V, out, h->ctl, h->res, 0, 1.0, s, form, Af));
+      HIP_TRY(sweep(form));
       HIP_TRY(hipEventRecord(h->ev1, s));
       HIP_TRY(hipEventSynchronize(h->ev1));
       HIP_TRY(hipEventElapsedTime(&ms[r], h->ev0, h->ev1));
@@ -596,28 +684,28 @@ int vi_solve(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, void* hip_st
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const Model& M = h->M;
-  int slab_t = h->slab_t;
-  if (slab_t < 0) {
-    const int cached = tune_lookup(M);
-    slab_t = cached >= 0 ? cached : (mdpvi::exact_shape(M) ? 0 : mdpvi::slab_digits(M));
-  }
+  mdpvi::TileShape S{};
+  const int form = vi_form(h, &S);
   double* A[2] = {nullptr, nullptr};
-  if (slab_t == 0 && mdpvi::exact_shape(M)) {
-    if (!h->abuf && hipMalloc(reinterpret_cast<void**>(&h->abuf), 2 * (M.n_occ + 1) * sizeof(double)) != hipSuccess) {
-      h->abuf = nullptr;
-      return fail(MDPVI_ENOMEM, "hipMalloc of the arrival-term arrays failed");
-    }
-    A[0] = h->abuf;
-    A[1] = h->abuf + M.n_occ + 1;
-    HIP_TRY(mdpvi::launch_arrival_init(M, V, A[0], A[1], s));
+  if ((form == 0 && mdpvi::exact_shape(M)) || is_tile_form(form)) {
+    int arc = arrival_arrays(h, V, s, A);
+    if (arc) return arc;
   }
+  if (is_tile_form(form))
+    return run_loop<float>(h, V, tol, max_iter, s, st, 8.0 * M.n_states,
+                           static_cast<double>(h->feasible_pairs),
+                           [&](long long j, float* in, float* out) {
+                             return mdpvi::launch_vi_tile(M, S, in, out, A[j & 1], A[(j + 1) & 1], h->ctl,
+                                                          h->res, j, tol, s);
+                           },
+                           false, S.grid);
   return run_loop<float>(h, V, tol, max_iter, s, st, 8.0 * M.n_states,
                          static_cast<double>(h->feasible_pairs),
                          [&](long long j, float* in, float* out) {
-                           return mdpvi::launch_vi_sweep(M, in, out, h->ctl, h->res, j, tol, s, slab_t,
+                           return mdpvi::launch_vi_sweep(M, in, out, h->ctl, h->res, j, tol, s, form,
                                                          A[0] ? A : nullptr);
                          },
-                         false, mdpvi::vi_sweep_grid(M, slab_t));
+                         false, mdpvi::vi_sweep_grid(M, form));
 }
 
 int policy_extract(mdpvi_mdp_t h, const float* V, uint8_t* pi, float* gap, void* hip_stream) {
@@ -647,6 +735,25 @@ int policy_eval(mdpvi_mdp_t h, const uint8_t* pi, double* V, double tol, int64_t
   HIP_TRY(hipStreamSynchronize(s));
   if (h->ctl_host->flag)
     return fail(MDPVI_EINVAL, "policy has an action that is not feasible in its state");
+  // the tile form where it applies and is worthwhile, or where the handle
+  // asks for it; the direct form otherwise
+  mdpvi::TileShape S{};
+  if (eval_form(h, &S) != 0) {
+    const size_t per = static_cast<size_t>(M.n_occ) + mdpvi::kSentinel;
+    if (!h->abuf && hipMalloc(reinterpret_cast<void**>(&h->abuf), 2 * per * sizeof(double)) != hipSuccess) {
+      h->abuf = nullptr;
+      return fail(MDPVI_ENOMEM, "hipMalloc of the arrival-term arrays failed");
+    }
+    double* A[2] = {h->abuf, h->abuf + per};
+    HIP_TRY(mdpvi::launch_eval_arrival_init(M, V, A[0], s));
+    return run_loop<double>(h, V, tol, max_iter, s, st, 17.0 * M.n_states,
+                            static_cast<double>(M.n_states),
+                            [&](long long j, double* in, double* out) {
+                              return mdpvi::launch_eval_tile(M, S, pi, in, out, A[j & 1], A[(j + 1) & 1],
+                                                             h->ctl, h->res, j, tol, s);
+                            },
+                            false, S.grid);
+  }
   return run_loop<double>(h, V, tol, max_iter, s, st, 17.0 * M.n_states,
                           static_cast<double>(M.n_states),
                           [&](long long j, double* in, double* out) {

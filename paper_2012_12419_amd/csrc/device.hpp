@@ -35,6 +35,16 @@ __device__ __forceinline__ int ld_u8(BufView v, uint32_t lane_off, uint32_t uni_
   return static_cast<int>(__builtin_amdgcn_raw_buffer_load_b8(v.r, lane_off, uni_off, 0));
 }
 
+typedef unsigned int U32x2 __attribute__((__vector_size__(8)));
+
+__device__ __forceinline__ void st_f32(BufView v, float x, uint32_t lane_off, uint32_t uni_off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), v.r, lane_off, uni_off, 0);
+}
+
+__device__ __forceinline__ void st_f64(BufView v, double x, uint32_t lane_off, uint32_t uni_off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, x), v.r, lane_off, uni_off, 0);
+}
+
 // Digits n_0..n_{K-1} of occupancy index o (host 0 fastest).
 template <int KMAX, typename Idx>
 __device__ __forceinline__ void decode(const Model& M, Idx o, int (&n)[KMAX]) {

@@ -16,15 +16,16 @@ hipError_t launch_ctl_init(Ctl* ctl, double* res, hipStream_t s);
 // V^{j+1} = T V^j (Vin -> Vout), residual into the words of sweep j; a
 // no-op once the stopping test has passed.  slab_t > 0 selects the LDS slab
 // form with that many low digits per slab (see slab_digits), 0 the direct form.
-// A: the two FP64 arrival-term arrays (n_occ + 1 doubles each) of the
+// A: the two FP64 arrival-term arrays (n_occ + kSentinel doubles each) of the
 // exact-shape direct form (sweep j reads A[j % 2], writes A[(j + 1) % 2]);
 // NULL uses the forms without them.
 hipError_t launch_vi_sweep(const Model& M, const float* Vin, float* Vout, Ctl* ctl, double* res,
                            long long j, double tol, hipStream_t s, int slab_t, double* const* A);
 // True when the exact-shape direct form (with arrival-term arrays) applies.
 bool exact_shape(const Model& M);
-// A0(o) = sum_e lambda_e/Lam V(o, e) for every occupancy; A0[n_occ] =
-// A1[n_occ] = -inf (each array holds n_occ + 1 doubles).
+// A0(o) = sum_e lambda_e/Lam V(o, e) for every occupancy; entries n_occ ..
+// n_occ + kSentinel - 1 of A0 and A1 = -inf (each array holds n_occ +
+// kSentinel doubles).
 hipError_t launch_arrival_init(const Model& M, const float* V, double* A0, double* A1, hipStream_t s);
 // Workgroups of one value-iteration sweep in the given form.
 uint32_t vi_sweep_grid(const Model& M, int slab_t);
@@ -33,6 +34,22 @@ uint32_t vi_sweep_grid(const Model& M, int slab_t);
 constexpr uint64_t kSlabLds = 40 * 1024;
 constexpr uint64_t kMinSlabs = 512;
 int slab_digits(const Model& M);
+
+// Tile form (tile_vi.hip, tile_eval.hip).  *_shape fills S and returns
+// false when the form does not apply to M.  The value-iteration tile reads
+// and writes the FP64 arrival-term arrays like the exact-shape direct form
+// (n_occ + kSentinel doubles each); the evaluation tile uses two FP64
+// arrival-term arrays of n_occ doubles, the first set from the initial
+// iterate by launch_eval_arrival_init.
+struct TileShape;
+bool vi_tile_shape(const Model& M, TileShape* S);
+hipError_t launch_vi_tile(const Model& M, const TileShape& S, const float* Vin, float* Vout, const double* Ain,
+                          double* Aout, Ctl* ctl, double* res, long long j, double tol, hipStream_t s);
+bool eval_tile_shape(const Model& M, TileShape* S);
+hipError_t launch_eval_arrival_init(const Model& M, const double* V, double* A, hipStream_t s);
+hipError_t launch_eval_tile(const Model& M, const TileShape& S, const uint8_t* pi, const double* Vin,
+                            double* Vout, const double* Ain, double* Aout, Ctl* ctl, double* res, long long j,
+                            double tol, hipStream_t s);
 
 // Greedy extraction from FP32 or FP64 values.
 hipError_t launch_extract_f32(const Model& M, const float* V, uint8_t* pi, float* gap,

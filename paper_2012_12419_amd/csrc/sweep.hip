@@ -30,6 +30,7 @@
 #include "device.hpp"
 #include "kernels.hpp"
 #include "sweep_impl.hpp"
+#include "tile.hpp"
 
 namespace mdpvi {
 
@@ -231,12 +232,13 @@ __global__ __launch_bounds__(kBlock) void vi_exact_kernel(Model M, const float* 
 }
 
 // A(o) = sum_e lambda_e/Lam V(o, e) of the initial iterate (the FMA chain of
-// backup_arrival) into A0, and the -inf sentinel A[n_occ] into both arrays.
+// backup_arrival) into A0, and the -inf sentinel block A[n_occ .. n_occ +
+// kSentinel) into both arrays.
 __global__ void arrival_init_kernel(Model M, const float* __restrict__ V, double* __restrict__ A0,
                                     double* __restrict__ A1) {
   const uint64_t o = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (o == static_cast<uint64_t>(M.n_occ)) {
-    A0[o] = -INFINITY;   // sentinel read by placements without room
+  if (o >= static_cast<uint64_t>(M.n_occ) && o < static_cast<uint64_t>(M.n_occ) + kSentinel) {
+    A0[o] = -INFINITY;   // read by placements without room
     A1[o] = -INFINITY;
   }
   if (o >= static_cast<uint64_t>(M.n_occ)) return;
@@ -248,14 +250,16 @@ __global__ void arrival_init_kernel(Model M, const float* __restrict__ V, double
 }
 
 hipError_t launch_arrival_init(const Model& M, const float* V, double* A0, double* A1, hipStream_t s) {
-  const uint32_t grid = static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + 256) / 256);
+  const uint32_t grid = static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + kSentinel + 255) / 256);
   hipLaunchKernelGGL(arrival_init_kernel, dim3(grid), dim3(256), 0, s, M, V, A0, A1);
   return hipGetLastError();
 }
 
+// Every byte offset of the exact-shape forms fits 31 bits: values (FP32,
+// n_states) and arrival terms (FP64, n_occ + kSentinel).
 bool exact_shape(const Model& M) {
-  return M.n_states < (int64_t{1} << 29) && M.K >= 1 && M.K <= 8 && M.J >= 1 && M.J <= 3 &&
-         M.n_sizes == M.J;
+  return M.n_states < (int64_t{1} << 29) && M.n_occ + kSentinel < (int64_t{1} << 28) && M.K >= 1 &&
+         M.K <= 8 && M.J >= 1 && M.J <= 3 && M.n_sizes == M.J;
 }
 
 template <int K, int J>

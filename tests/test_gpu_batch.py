@@ -45,8 +45,17 @@ def test_batch_mixed_vs_oracle(mdpvi):
     for i, p in enumerate(insts):
         print(f"instance {i}: K={p.K} C={p.C} J={p.J} N={p.num_states} sweeps={its[i]}", flush=True)
         assert res[i] < 1e-7
-        star = vi.value_iteration(p, 1e-12).V
-        vi_close(Vh[b.offsets[i]:b.offsets[i + 1]], star)
+        Vi = Vh[b.offsets[i]:b.offsets[i + 1]]
+        if p.num_states <= 20_000:
+            star = vi.value_iteration(p, 1e-12).V
+            vi_close(Vi, star)
+        else:
+            # one oracle sweep from the GPU's values: a fixed point up to one
+            # FP32 rounding plus gamma times the stopping residual
+            Vg = Vi.astype(np.float64)
+            TV = vi.bellman(p, Vg)
+            half_ulp = np.spacing(np.abs(Vi)).astype(np.float64) / 2
+            assert np.all(np.abs(TV - Vg) <= 1.0001 * half_ulp + 1e-7)
 
 
 def test_batch_equals_per_instance(mdpvi):

@@ -228,7 +228,34 @@ FORM_CASES = [("small_parity", W.small_parity()),
               ("K16_C1", W.make(16, 1, (1,), (1.5,), 0.1, 0.01, (1.0,), 0.9)),
               ("J8_K3C8", W.make(3, 8, tuple(range(1, 9)), [0.1 * (j + 1) for j in range(8)], 0.1, 0.02,
                                  [0.8 * (j + 1) for j in range(8)], 0.9)),
-              ("gradient", W.gradient_instance())]
+              ("gradient", W.gradient_instance()),
+              # tile form (forced where the automatic choice would not take it):
+              # T = 3 for value iteration, T = 2 for evaluation (LDS budget)
+              ("tile_K4C12J3", W.make(4, 12, (3, 1, 2), (0.4, 0.7, 0.2), 0.09, 0.03, (2.0, 0.7, 1.6), 0.96)),
+              ("tile_K4C9J3", W.make(4, 9, (1, 2, 3), (0.5, 0.4, 0.3), 0.1, 0.02, (1.0, 2.2, 3.1), 0.95)),
+              # T = 4; size 3 fits only when a host holds <= 1 unit
+              ("tile_K6C4J2", W.make(6, 4, (1, 3), (0.5, 0.3), 0.12, 0.03, (1.0, 2.9), 0.94,
+                                     reject_cost=(0.1, 0.4))),
+              # K = 3: T = 2, 64 occupancies per tile (idle threads)
+              ("tile_K3C7J1", W.make(3, 7, (2,), (0.9,), 0.1, 0.05, (1.5,), 0.93)),
+              # the automatic choice takes the tile form: 256 tiles of 256 occupancies
+              ("tile_auto_K8C3J2", W.make(8, 3, (1, 2), (0.7, 0.4), 0.15, 0.03, (1.0, 2.2), 0.92))]
+
+def _forms(mdpvi, inst):
+    forms = [0]
+    occ = 1
+    for t in range(1, inst.K):
+        occ *= inst.C + 1
+        if occ * (8 + 4 * inst.J) <= 64 * 1024:
+            forms.append(t)
+    mdp = mdpvi.MDP.from_instance(inst)
+    try:
+        mdp.set_sweep_form(mdpvi.FORM_TILE)
+        # one workgroup per tile; two and five workgroups per CU walking tiles
+        forms += [mdpvi.FORM_TILE, mdpvi.FORM_TILE + 2, mdpvi.FORM_TILE + 5]
+    except mdpvi.MdpviError as e:
+        assert e.code == mdpvi.EINVAL
+    return forms
 
 
 @pytest.mark.parametrize("name,inst", FORM_CASES, ids=[c[0] for c in FORM_CASES])
@@ -236,12 +263,9 @@ def test_sweep_forms_bit_identical(mdpvi, name, inst):
     # every sweep kernel form computes the same arithmetic in the same order
     import torch
     mdp = mdpvi.MDP.from_instance(inst)
-    forms = [0]
-    occ = 1
-    for t in range(1, inst.K):
-        occ *= inst.C + 1
-        if occ * (8 + 4 * inst.J) <= 64 * 1024:
-            forms.append(t)
+    forms = _forms(mdpvi, inst)
+    if name.startswith("tile") or name == "gradient":
+        assert mdpvi.FORM_TILE in forms
     ref = None
     for f in forms + [-1]:
         mdp.set_sweep_form(f)
@@ -257,6 +281,56 @@ def test_sweep_forms_bit_identical(mdpvi, name, inst):
         else:
             assert got[1] == ref[1]
             assert np.array_equal(got[0], ref[0])
+
+
+@pytest.mark.parametrize("name,inst", FORM_CASES, ids=[c[0] for c in FORM_CASES])
+def test_eval_forms_bit_identical(mdpvi, name, inst):
+    # fixed-policy evaluation: the direct and tile forms give the same bits;
+    # the result is the oracle's V_pi
+    import torch
+    mdp = mdpvi.MDP.from_instance(inst)
+    forms = [f for f in _forms(mdpvi, inst) if f == 0 or f >= mdpvi.FORM_TILE]
+    pi = mdp.policy_greedy("least_loaded")
+    ref = None
+    for f in forms + [-1]:
+        mdp.set_sweep_form(f)
+        V = torch.zeros(mdp.num_states, dtype=torch.float64, device="cuda")
+        _, st = mdp.policy_eval(pi, V, tol=1e-11)
+        got = (V.cpu().numpy().view(np.uint64).copy(), st["iterations"])
+        print(f"{name}: eval form {f}: {st['iterations']} sweeps", flush=True)
+        if ref is None:
+            ref = got
+            if inst.num_states < 400_000:
+                V_o = vi.policy_eval(inst, pi.cpu().numpy(), tol=1e-13)
+                assert np.max(np.abs(V.cpu().numpy() - V_o)) <= EVAL_REL * np.max(np.abs(V_o)) * 10
+        else:
+            assert got[1] == ref[1]
+            assert np.array_equal(got[0], ref[0])
+
+
+def test_tile_full_size_matches_direct(mdpvi):
+    # the 5.3M-state instance: 20 value-iteration sweeps and 20 evaluation
+    # sweeps in the tile and the direct form give the same bits
+    import torch
+    inst = W.large_single()
+    mdp = mdpvi.MDP.from_instance(inst)
+    pi = mdp.policy_greedy("least_loaded")
+    outs = {}
+    for f in (0, mdpvi.FORM_TILE, mdpvi.FORM_TILE + 3):
+        mdp.set_sweep_form(f)
+        V = torch.zeros(mdp.num_states, device="cuda")
+        with pytest.raises(mdpvi.MdpviError) as ei:
+            mdp.vi_solve(V, tol=1e-30, max_iter=20)
+        assert ei.value.code == mdpvi.ENOCONV
+        Ve = torch.zeros(mdp.num_states, dtype=torch.float64, device="cuda")
+        with pytest.raises(mdpvi.MdpviError) as ei:
+            mdp.policy_eval(pi, Ve, tol=1e-30, max_iter=20)
+        assert ei.value.code == mdpvi.ENOCONV
+        outs[f] = (V.cpu().numpy().view(np.uint32).copy(), Ve.cpu().numpy().view(np.uint64).copy())
+        print(f"large_single form {f}: done", flush=True)
+    for f in (mdpvi.FORM_TILE, mdpvi.FORM_TILE + 3):
+        assert np.array_equal(outs[0][0], outs[f][0])
+        assert np.array_equal(outs[0][1], outs[f][1])
 
 
 def test_autotune_cache(mdpvi, tmp_path):
