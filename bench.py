@@ -89,6 +89,94 @@ def batched_vs_per_instance(mdpvi, n: int, tol: float) -> dict:
             "speedup": t_single / t_batch, "max_sweeps": max(its)}
 
 
+def _sub_solution(p):
+    """A constant sub-solution of the Bellman operator: the least one-step
+    reward over the discount horizon (value iteration from it is monotone)."""
+    import numpy as np
+    lam = np.asarray(p.lam)
+    Lam = lam.sum() + p.K * p.C * p.mu + p.K * p.nu
+    return -lam.sum() / Lam * max(p.reject_cost) / (1 - p.gamma)
+
+
+def gradient_workloads(mdpvi, n_batch: int, tol: float) -> dict:
+    """The adjoint gradient (dJ/dtheta, theta = lambda, mu, nu, r) on the
+    gradient instance (K=5 C=10 J=2, 322,102 states), and the batched
+    pipeline on the first n_batch instances of the parameter sweep: value
+    iteration, greedy policy, FP64 evaluation with improvement steps until the
+    policy is stable, adjoint gradient, and the least-loaded heuristic's FP64
+    evaluation, all as batched calls.  Wall time on one stream."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+
+    def single():
+        inst = W.gradient_instance()
+        mdp = mdpvi.MDP.from_instance(inst)
+        V = torch.zeros(mdp.num_states, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mdp.vi_solve(V, tol=tol)
+        pi, _ = mdp.policy_extract(V, want_gap=False)
+        Vp = V.double()
+        for _ in range(8):
+            mdp.policy_eval(pi, Vp, tol=1e-12)
+            pi2, _ = mdp.policy_extract(Vp, want_gap=False)
+            if torch.equal(pi2, pi):
+                break
+            pi = pi2
+        g, Jv, _, st = mdp.vi_adjoint(pi, Vp, tol=1e-10)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, g, Jv, st
+
+    single()   # first-use allocations
+    t_single, g, Jv, st_adj = single()
+
+    insts = W.batch(512, seed=3)[:n_batch]
+    b = mdpvi.Batch(insts)
+    N = b.num_states
+    lb = torch.zeros(N, device="cuda")
+    for i, p in enumerate(insts):
+        lb[b.offsets[i]:b.offsets[i + 1]] = _sub_solution(p)
+
+    def batched():
+        V = lb.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.vi_solve(V, tol=tol)
+        pi, _ = b.policy_extract(V, want_gap=False)
+        Vp = V.double()
+        for _ in range(8):
+            b.policy_eval(pi, Vp, tol=1e-12)
+            pi2, _ = b.policy_extract(Vp, want_gap=False)
+            if torch.equal(pi2, pi):
+                break
+            pi = pi2
+        grads, objs, _, _, _ = b.vi_adjoint(pi, Vp, [p.J for p in insts], tol=1e-10)
+        pig = b.policy_greedy("least_loaded")
+        Vg, _, _, _ = b.policy_eval(pig, tol=1e-12)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, objs, Vg
+
+    batched()
+    t_batch, objs, Vg = batched()
+    Vg_h = Vg.cpu().numpy()
+    gaps = []
+    for i, p in enumerate(insts):
+        c = np.asarray(p.lam) / sum(p.lam)
+        n_occ = (p.C + 1) ** p.K
+        J_g = float(sum(c[e] * Vg_h[b.offsets[i] + e * n_occ] for e in range(p.J)))
+        gaps.append(objs[i] - J_g)
+    return {"single": {"workload": "gradient: K=5 C=10 J=2 sizes(1,2), gamma 0.98: 322,102 states",
+                       "seconds": t_single, "gradients_per_s": 1.0 / t_single, "J": Jv,
+                       "adjoint_sweeps": st_adj["iterations"], "adjoint_seconds": st_adj["seconds"],
+                       "dJ_dtheta": list(g)},
+            "batched": {"instances": n_batch, "states": N, "seconds": t_batch,
+                        "gradients_per_s": n_batch / t_batch,
+                        "mean_J_opt_minus_J_greedy": float(np.mean(gaps)),
+                        "min_J_opt_minus_J_greedy": float(np.min(gaps))}}
+
+
 def traffic_record(kernel_files, name: str):
     """HBM traffic of a kernel from the committed counter record, or None when
     the record is missing or its sources changed since the counters were taken."""
@@ -144,6 +232,8 @@ def main() -> int:
                          "16+w tile form (w workgroups per CU, 0: one per tile)")
     ap.add_argument("--batch", type=int, default=512,
                     help="instances of the batched-vs-per-instance comparison (0: skip)")
+    ap.add_argument("--grad-batch", type=int, default=256,
+                    help="instances of the batched gradient pipeline (0: skip the gradient fields)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -295,6 +385,8 @@ def main() -> int:
     del Vh
     if args.batch:
         out["batched_vs_per_instance"] = batched_vs_per_instance(mdpvi, args.batch, args.tol)
+    if args.grad_batch:
+        out["gradient"] = gradient_workloads(mdpvi, args.grad_batch, args.tol)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps)
     print(json.dumps(out), flush=True)
