@@ -89,6 +89,24 @@ def batched_vs_per_instance(mdpvi, n: int, tol: float) -> dict:
             "speedup": t_single / t_batch, "max_sweeps": max(its)}
 
 
+def bsdi_comparison(mdp, N: int, tol: float, inners=(1, 2, 4, 8)) -> dict:
+    """Block-asynchronous value iteration (the paper's BSDI) against Jacobi
+    on the same instance: passes and device seconds to the same tolerance
+    from V = 0 (the Jacobi figure is the timed steps' time to tol)."""
+    import torch
+    out = {"inner": [], "passes": [], "seconds": [], "us_per_pass": []}
+    V = torch.zeros(N, dtype=torch.float32, device="cuda")
+    mdp.vi_solve_bsdi(V, tol=tol, inner=2)   # first-use allocations
+    for inner in inners:
+        V.zero_()
+        st = mdp.vi_solve_bsdi(V, tol=tol, inner=inner)
+        out["inner"].append(inner)
+        out["passes"].append(st["iterations"])
+        out["seconds"].append(st["seconds"])
+        out["us_per_pass"].append(st["seconds"] / st["iterations"] * 1e6)
+    return out
+
+
 def _sub_solution(p):
     """A constant sub-solution of the Bellman operator: the least one-step
     reward over the discount horizon (value iteration from it is monotone)."""
@@ -232,6 +250,8 @@ def main() -> int:
                          "16+w tile form (w workgroups per CU, 0: one per tile)")
     ap.add_argument("--batch", type=int, default=512,
                     help="instances of the batched-vs-per-instance comparison (0: skip)")
+    ap.add_argument("--no-bsdi", dest="bsdi", action="store_false",
+                    help="skip the block-asynchronous (BSDI) comparison")
     ap.add_argument("--grad-batch", type=int, default=256,
                     help="instances of the batched gradient pipeline (0: skip the gradient fields)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -291,6 +311,13 @@ def main() -> int:
         recs.append(step())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+
+    bsdi = None
+    if args.bsdi:
+        try:
+            bsdi = bsdi_comparison(mdp, N, args.tol)
+        except mdpvi.MdpviError as e:
+            bsdi = {"skipped": str(e)}
 
     # one more step with every sweep bracketed by HIP events on the solver's
     # stream (outside the timed region): per-kernel durations
@@ -381,6 +408,7 @@ def main() -> int:
         "improvement_step_changed_states": changed,
         "roofline": roof,
         "kernels": kernels,
+        "bsdi_vs_jacobi": bsdi,
     }
     del Vh
     if args.batch:

@@ -217,6 +217,25 @@ int vi_solve_batch(mdpvi_batch_t b, float *V, double tol, int64_t max_iter,
                    void *hip_stream, mdpvi_stats *st, int64_t *iterations,
                    double *residuals);
 
+/* Block-asynchronous value iteration (the paper's BSDI, Alg. 4) on the tiles
+ * of the tile form: a pass stages each tile of (C+1)^T occupancies (all
+ * classes) in LDS and runs `inner` synchronous episodes of the Bellman backup
+ * of Eq. (18) on it, in which a successor inside the tile (along a low
+ * digit, the state itself, or the reset of an empty high-digit host)
+ * contributes the tile's latest value and a successor outside the tile the
+ * previous pass's value; the pass writes the last episode back.  Passes
+ * repeat until the largest change of a pass is < tol.  inner = 1 is
+ * vi_solve's Jacobi iteration, bit for bit.  The iterates differ from
+ * Jacobi's for inner > 1, but every episode applies the same monotone FP32
+ * operator, so from a sub-solution both increase to the same FP32 fixed
+ * point.  V: device float[N], in V^0, out the last pass.  st->iterations
+ * counts passes, st->backups counts feasible pairs times passes times
+ * inner.  Needs K in 3..8, J <= 3 distinct sizes and a tile (T >= 2) whose
+ * two LDS images fit 64 KB.  Errors: as vi_solve; MDPVI_EINVAL for inner
+ * outside 1..1024 or a shape the form does not cover.                       */
+int vi_solve_bsdi(mdpvi_mdp_t h, float *V, double tol, int64_t max_iter, int32_t inner,
+                  void *hip_stream, mdpvi_stats *st);
+
 /* Choice of the sweep kernels for this handle (a tuning knob; every form
  * computes bit-identical iterates).  slab_digits = -1: automatic (the
  * default); 0: the direct forms (every neighbour read from global memory);

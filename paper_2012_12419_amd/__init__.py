@@ -91,6 +91,7 @@ SIGNATURES = {
                                         ctypes.POINTER(Stats), ctypes.POINTER(_c_int64)]),
     "mdp_set_timing": (ctypes.c_int, [_vp, _c_int32]),
     "mdp_set_sweep_form": (ctypes.c_int, [_vp, _c_int32]),
+    "vi_solve_bsdi": (ctypes.c_int, [_vp, _vp, _c_double, _c_int64, _c_int32, _vp, ctypes.POINTER(Stats)]),
     "mdp_sweep_forms": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32)]),
     "mdp_autotune": (ctypes.c_int, [_vp, _vp, _c_int32, _vp, ctypes.POINTER(_c_int32),
                                     ctypes.POINTER(_c_double)]),
@@ -231,6 +232,16 @@ class MDP:
         v = _dev_tensor(V, torch.float32, self.num_states, "V")
         _check(load().vi_solve(self._h, v, float(tol), int(max_iter), _stream_ptr(stream),
                                ctypes.byref(st)), st)
+        return st.as_dict()
+
+    def vi_solve_bsdi(self, V, tol: float = 1e-6, inner: int = 4, max_iter: int = 1_000_000,
+                      stream=None) -> dict:
+        """Block-asynchronous passes of `inner` in-tile episodes (vi_solve_bsdi)."""
+        import torch
+        st = Stats()
+        v = _dev_tensor(V, torch.float32, self.num_states, "V")
+        _check(load().vi_solve_bsdi(self._h, v, float(tol), int(max_iter), int(inner), _stream_ptr(stream),
+                                    ctypes.byref(st)), st)
         return st.as_dict()
 
     def policy_extract(self, V, pi=None, gap=None, want_gap: bool = True, stream=None):

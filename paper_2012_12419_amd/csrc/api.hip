@@ -708,6 +708,32 @@ int vi_solve(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, void* hip_st
                          false, mdpvi::vi_sweep_grid(M, form));
 }
 
+int vi_solve_bsdi(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, int32_t inner, void* hip_stream,
+                  mdpvi_stats* st) {
+  if (!h || !V) return fail(MDPVI_EINVAL, "NULL handle or value array");
+  if (!(tol > 0)) return fail(MDPVI_EINVAL, "tol=%g must be > 0", tol);
+  if (max_iter < 1) return fail(MDPVI_EINVAL, "max_iter=%lld must be >= 1", (long long)max_iter);
+  if (inner < 1 || inner > 1024) return fail(MDPVI_EINVAL, "inner=%d outside [1, 1024]", inner);
+  const Model& M = h->M;
+  mdpvi::TileShape S{};
+  if (!mdpvi::vi_bsdi_shape(M, &S))
+    return fail(MDPVI_EINVAL, "the block-asynchronous form needs an exact shape (K in 3..8, J <= 3 distinct "
+                              "sizes) whose tile fits the LDS budget");
+  int rc = ensure_scratch(h, static_cast<size_t>(M.n_states) * sizeof(float));
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  double* A[2] = {nullptr, nullptr};
+  rc = arrival_arrays(h, V, s, A);
+  if (rc) return rc;
+  return run_loop<float>(h, V, tol, max_iter, s, st, 8.0 * M.n_states,
+                         static_cast<double>(h->feasible_pairs) * inner,
+                         [&](long long j, float* in, float* out) {
+                           return mdpvi::launch_vi_bsdi(M, S, inner, in, out, A[j & 1], A[(j + 1) & 1], h->ctl,
+                                                        h->res, j, tol, s);
+                         },
+                         false, S.grid);
+}
+
 int policy_extract(mdpvi_mdp_t h, const float* V, uint8_t* pi, float* gap, void* hip_stream) {
   if (!h || !V || !pi) return fail(MDPVI_EINVAL, "NULL handle, value or policy array");
   HIP_TRY(mdpvi::launch_extract_f32(h->M, V, pi, gap, static_cast<hipStream_t>(hip_stream)));

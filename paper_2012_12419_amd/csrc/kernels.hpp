@@ -45,6 +45,12 @@ struct TileShape;
 bool vi_tile_shape(const Model& M, TileShape* S);
 hipError_t launch_vi_tile(const Model& M, const TileShape& S, const float* Vin, float* Vout, const double* Ain,
                           double* Aout, Ctl* ctl, double* res, long long j, double tol, hipStream_t s);
+// Block-asynchronous passes on tiles (two LDS images each): `inner`
+// episodes per pass, successors outside the tile from the previous pass.
+bool vi_bsdi_shape(const Model& M, TileShape* S);
+hipError_t launch_vi_bsdi(const Model& M, const TileShape& S, int inner, const float* Vin, float* Vout,
+                          const double* Ain, double* Aout, Ctl* ctl, double* res, long long j, double tol,
+                          hipStream_t s);
 bool eval_tile_shape(const Model& M, TileShape* S);
 hipError_t launch_eval_arrival_init(const Model& M, const double* V, double* A, hipStream_t s);
 hipError_t launch_eval_tile(const Model& M, const TileShape& S, const uint8_t* pi, const double* Vin,

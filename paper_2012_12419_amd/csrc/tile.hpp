@@ -27,8 +27,9 @@ namespace mdpvi {
 // arrival array: a placement without room along a high digit reads entry
 // n_occ + i (i < tile size <= kSentinel).
 constexpr uint32_t kSentinel = 4096;
-// LDS bytes a tile may take.
+// LDS bytes a tile image may take (the block-asynchronous form holds two).
 constexpr uint32_t kTileLds = 48 * 1024;
+constexpr uint32_t kBsdiLds = 64 * 1024;
 
 struct TileShape {
   uint32_t occ;    // (C+1)^T occupancies per tile
@@ -58,17 +59,17 @@ __device__ __forceinline__ TileWalk tile_walk(const TileShape& S) {
   return TileWalk{lo + w, hi, gridDim.x / kNumXcd};
 }
 
-// The deepest tile (T in 2..min(4, K-1)) whose LDS image of bytes_per_occ
-// bytes per occupancy fits kTileLds (and, for the -inf sentinel block, at
-// most kSentinel occupancies); false if none, or if the shape is not an
-// exact one (K in 3..8, J <= 3 distinct sizes).
-inline bool tile_shape(const Model& M, uint32_t bytes_per_occ, TileShape* S) {
+// The deepest tile (T in 2..min(4, K-1)) whose LDS footprint of
+// bytes_per_occ bytes per occupancy fits lds_limit (and, for the -inf
+// sentinel block, at most kSentinel occupancies); false if none, or if the
+// shape is not an exact one (K in 3..8, J <= 3 distinct sizes).
+inline bool tile_shape(const Model& M, uint32_t bytes_per_occ, uint32_t lds_limit, TileShape* S) {
   if (M.K < 3 || M.K > 8 || M.J < 1 || M.J > 3 || M.n_sizes != M.J) return false;
   if (M.n_occ + kSentinel >= (int64_t{1} << 28)) return false;
   for (int T = (M.K - 1 < 4 ? M.K - 1 : 4); T >= 2; --T) {
     uint64_t occ = 1;
     for (int i = 0; i < T; ++i) occ *= static_cast<uint64_t>(M.R);
-    if (occ * bytes_per_occ <= kTileLds && occ <= kSentinel) {
+    if (occ * bytes_per_occ + 16 <= lds_limit && occ <= kSentinel) {
       S->occ = static_cast<uint32_t>(occ);
       S->n = static_cast<uint32_t>(static_cast<uint64_t>(M.n_occ) / occ);
       S->T = T;

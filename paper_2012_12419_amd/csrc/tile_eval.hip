@@ -160,7 +160,7 @@ __global__ void eval_arrival_init_kernel(Model M, const double* __restrict__ V, 
 }
 
 bool eval_tile_shape(const Model& M, TileShape* S) {
-  return M.n_states < (int64_t{1} << 28) && tile_shape(M, 8u * M.J + 8u, S);
+  return M.n_states < (int64_t{1} << 28) && tile_shape(M, 8u * M.J + 8u, kTileLds, S);
 }
 
 hipError_t launch_eval_arrival_init(const Model& M, const double* V, double* A, hipStream_t s) {

@@ -1,16 +1,151 @@
 // tile_vi.hip -- the value-iteration sweep (Eq. (18), Alg. 3 step 2) in the
-// tile form: a workgroup stages the values and FP64 arrival terms of its
+// tile form, and the block-asynchronous variant (the paper's BSDI, Alg. 4)
+// built on the same tiles.
+//
+// Tile form: a workgroup stages the values and FP64 arrival terms of its
 // (C+1)^T-occupancy tile in LDS, reads low-digit neighbours from LDS and
 // high-digit neighbours from global memory at workgroup-uniform offsets.
-//
 // Per state the backup is that of the exact-shape direct form (arrival terms
 // from the FP64 side array of the previous sweep, zero-weight stand-ins for
 // missing release neighbours, -inf for placements without room), in the same
 // order: bit-identical iterates.
+//
+// Block-asynchronous form: a pass stages the tile, runs `inner` episodes of
+// the same backup on it, each episode reading the tile's latest values from
+// LDS (its previous episode's results, a double-buffered synchronous update
+// inside the tile) and every successor outside the tile from the previous
+// pass in global memory, and writes the last episode's values back.  A
+// successor stays inside the tile when it moves along a low digit, when it is
+// the state itself (idle, paid cloud) and when it is the reset of a high-digit
+// host that is already empty.  The pass residual is the largest change
+// against the previous pass.  With inner = 1 a pass is one Jacobi sweep.
 #include "kernels.hpp"
 #include "tile.hpp"
 
 namespace mdpvi {
+
+// Workgroup-uniform data of one tile: its first occupancy, its high digits
+// and the byte offsets (relative to the tile base, in the scalar operand of a
+// buffer load) of its high-digit neighbours.
+template <int K, int J, int T>
+struct TileHigh {
+  uint32_t o0;
+  int nh[K - T];
+  int load_high;
+  uint32_t hd4[K - T];      // release neighbour (the tile itself when n_k = 0: weight 0)
+  uint32_t hr4[K - T];      // reset neighbour
+  uint32_t ha8[K - T][J];   // placement, or the -inf sentinel block
+};
+
+template <int K, int J, int T>
+__device__ __forceinline__ void tile_high_setup(const Model& M, uint32_t tb, TileHigh<K, J, T>& H) {
+  constexpr int NH = K - T;
+  const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
+  H.o0 = tile_high<K, T>(M, tb, H.nh);
+  H.load_high = 0;
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+    const uint32_t st = static_cast<uint32_t>(M.stride[T + h]);
+    H.hd4[h] = (H.nh[h] > 0 ? H.o0 - st : H.o0) * 4u;
+    H.hr4[h] = (H.o0 - static_cast<uint32_t>(H.nh[h]) * st) * 4u;
+#pragma unroll
+    for (int e = 0; e < J; ++e) {
+      const int s = M.size[e];
+      H.ha8[h][e] = H.nh[h] + s <= M.C ? (H.o0 + static_cast<uint32_t>(s) * st) * 8u : nocc * 8u;
+    }
+    H.load_high += H.nh[h];
+  }
+}
+
+// Backup of tile occupancy i: own values, low-digit neighbours and in-tile
+// arrival terms from the LDS image (Vl [J][occ], Al [occ + 1] with -inf at
+// occ), high-digit neighbours from global memory.  With SelfLatest the reset
+// of an empty high-digit host, which is the state itself, takes the state's
+// LDS value (the block-asynchronous form; in a Jacobi sweep both are the
+// same).  Returns the new values vn, the new arrival term anew = sum_e
+// lambda_e/Lam vn_e and the values vs the backup read at the state itself.
+template <int K, int J, int T, bool SelfLatest>
+__device__ __forceinline__ void tile_backup(const Model& M, const TileHigh<K, J, T>& H, uint32_t occ,
+                                            const float* Vl, const double* Al, BufView vin, BufView ain,
+                                            uint32_t i, float (&vs)[J], float (&vn)[J], double& anew) {
+  constexpr int NH = K - T;
+  const uint32_t cls = static_cast<uint32_t>(M.n_occ) * 4u;
+  float vd[K][J], vr[K][J];
+  double aa[K][J];
+  const uint32_t i4 = i * 4u, i8 = i * 8u;
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+#pragma unroll
+    for (int e = 0; e < J; ++e) {
+      vd[T + h][e] = ld_f32(vin, i4, H.hd4[h] + e * cls);
+      vr[T + h][e] = ld_f32(vin, i4, H.hr4[h] + e * cls);
+      aa[T + h][e] = ld_f64(ain, i8, H.ha8[h][e]);
+    }
+  }
+  int n[K];
+  tile_low<T>(M, i, n);
+#pragma unroll
+  for (int h = 0; h < NH; ++h) n[T + h] = H.nh[h];
+  int load = H.load_high;
+#pragma unroll
+  for (int k = 0; k < T; ++k) load += n[k];
+#pragma unroll
+  for (int e = 0; e < J; ++e) vs[e] = Vl[e * occ + i];
+  if constexpr (SelfLatest) {
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+#pragma unroll
+      for (int e = 0; e < J; ++e) vr[T + h][e] = H.nh[h] == 0 ? vs[e] : vr[T + h][e];
+    }
+  }
+  const double a_rej = Al[i];
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    const uint32_t st = static_cast<uint32_t>(M.stride[k]);
+    const uint32_t d = n[k] > 0 ? i - st : i;   // n_k = 0: the state itself, weight 0
+    const uint32_t r = i - static_cast<uint32_t>(n[k]) * st;
+#pragma unroll
+    for (int e = 0; e < J; ++e) {
+      vd[k][e] = Vl[e * occ + d];
+      vr[k][e] = Vl[e * occ + r];
+      const int s = M.size[e];
+      aa[k][e] = Al[n[k] + s <= M.C ? i + static_cast<uint32_t>(s) * st : occ];
+    }
+  }
+  const double idle = M.mu_L * static_cast<double>(M.KC - load);
+  anew = 0.0;
+#pragma unroll
+  for (int e = 0; e < J; ++e) {
+    double ab = aa[0][e];
+#pragma unroll
+    for (int a = 1; a < K; ++a) ab = fmax(ab, aa[a][e]);
+    double D = idle * static_cast<double>(vs[e]);
+    double rs = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      D = fma(M.mu_L * n[k], static_cast<double>(vd[k][e]), D);
+      rs += static_cast<double>(vr[k][e]);
+    }
+    D = fma(M.nu_L, rs, D);
+    const double best = fmax(fma(M.gamma, a_rej, M.r_reject[e]), fma(M.gamma, ab, M.r_place[e]));
+    vn[e] = static_cast<float>(fma(M.gamma, D, best));
+    anew = fma(M.p[e], static_cast<double>(vn[e]), anew);
+  }
+}
+
+// Stages the tile's values and arrival terms into (Vl, Al) and sets the
+// sentinel Al[occ] = -inf.
+template <int J>
+__device__ __forceinline__ void tile_stage(const Model& M, uint32_t occ, uint32_t o0, BufView vin, BufView ain,
+                                           float* Vl, double* Al) {
+  const uint32_t cls = static_cast<uint32_t>(M.n_occ) * 4u;
+  for (uint32_t i = threadIdx.x; i < occ; i += kBlock) {
+#pragma unroll
+    for (int e = 0; e < J; ++e) Vl[e * occ + i] = ld_f32(vin, i * 4u, o0 * 4u + e * cls);
+    Al[i] = ld_f64(ain, i * 8u, o0 * 8u);
+  }
+  if (threadIdx.x == 0) Al[occ] = -INFINITY;
+}
 
 template <int K, int J, int T>
 __global__ __launch_bounds__(kBlock) void vi_tile_kernel(Model M, TileShape S, const float* __restrict__ Vin,
@@ -19,7 +154,6 @@ __global__ __launch_bounds__(kBlock) void vi_tile_kernel(Model M, TileShape S, c
                                                           double* __restrict__ Aout, Ctl* ctl, double* res,
                                                           long long j, double tol) {
   if (sweep_stopped<ResKind::kMax>(ctl, res, j, tol)) return;
-  constexpr int H = K - T;
   extern __shared__ double tile_lds[];
   const uint32_t occ = S.occ;
   double* Al = tile_lds;                                       // [occ + 1], -inf at occ
@@ -35,101 +169,92 @@ __global__ __launch_bounds__(kBlock) void vi_tile_kernel(Model M, TileShape S, c
   bool bad = false;
   const TileWalk tw = tile_walk(S);
   for (uint32_t tb = tw.first; tb < tw.end; tb += tw.step) {
-  int nh[H];
-  const uint32_t o0 = tile_high<K, T>(M, tb, nh);
-
-  for (uint32_t i = threadIdx.x; i < occ; i += kBlock) {
-#pragma unroll
-    for (int e = 0; e < J; ++e) Vl[e * occ + i] = ld_f32(vin, i * 4u, o0 * 4u + e * cls);
-    Al[i] = ld_f64(ain, i * 8u, o0 * 8u);
-  }
-  if (threadIdx.x == 0) Al[occ] = -INFINITY;
-  __syncthreads();
-
-  // high-digit neighbours: workgroup-uniform byte offsets of the tile base
-  uint32_t hd4[H], hr4[H], ha8[H][J];
-  int load_high = 0;
-#pragma unroll
-  for (int h = 0; h < H; ++h) {
-    const uint32_t st = static_cast<uint32_t>(M.stride[T + h]);
-    hd4[h] = (nh[h] > 0 ? o0 - st : o0) * 4u;   // n_k = 0: the state itself, weight 0
-    hr4[h] = (o0 - static_cast<uint32_t>(nh[h]) * st) * 4u;
-#pragma unroll
-    for (int e = 0; e < J; ++e) {
-      const int s = M.size[e];
-      ha8[h][e] = nh[h] + s <= M.C ? (o0 + static_cast<uint32_t>(s) * st) * 8u : nocc * 8u;
-    }
-    load_high += nh[h];
-  }
-
-  for (uint32_t i = threadIdx.x; i < occ; i += kBlock) {
-    float vd[K][J], vr[K][J];
-    double aa[K][J];
-    const uint32_t i4 = i * 4u, i8 = i * 8u;
-#pragma unroll
-    for (int h = 0; h < H; ++h) {
+    TileHigh<K, J, T> H;
+    tile_high_setup<K, J, T>(M, tb, H);
+    tile_stage<J>(M, occ, H.o0, vin, ain, Vl, Al);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < occ; i += kBlock) {
+      float vs[J], vn[J];
+      double anew;
+      tile_backup<K, J, T, false>(M, H, occ, Vl, Al, vin, ain, i, vs, vn, anew);
 #pragma unroll
       for (int e = 0; e < J; ++e) {
-        vd[T + h][e] = ld_f32(vin, i4, hd4[h] + e * cls);
-        vr[T + h][e] = ld_f32(vin, i4, hr4[h] + e * cls);
-        aa[T + h][e] = ld_f64(ain, i8, ha8[h][e]);
+        st_f32(vout, vn[e], i * 4u, H.o0 * 4u + e * cls);
+        const double dd = fabs(static_cast<double>(vn[e]) - static_cast<double>(vs[e]));
+        dmax = fmax(dmax, dd);
+        bad = bad || (dd != dd);
       }
+      st_f64(aout, anew, i * 8u, H.o0 * 8u);
     }
-    int n[K];
-    tile_low<T>(M, i, n);
-#pragma unroll
-    for (int h = 0; h < H; ++h) n[T + h] = nh[h];
-    int load = load_high;
-#pragma unroll
-    for (int k = 0; k < T; ++k) load += n[k];
-    float vs[J];
-#pragma unroll
-    for (int e = 0; e < J; ++e) vs[e] = Vl[e * occ + i];
-    const double a_rej = Al[i];
-#pragma unroll
-    for (int k = 0; k < T; ++k) {
-      const uint32_t st = static_cast<uint32_t>(M.stride[k]);
-      const uint32_t d = n[k] > 0 ? i - st : i;
-      const uint32_t r = i - static_cast<uint32_t>(n[k]) * st;
-#pragma unroll
-      for (int e = 0; e < J; ++e) {
-        vd[k][e] = Vl[e * occ + d];
-        vr[k][e] = Vl[e * occ + r];
-        const int s = M.size[e];
-        aa[k][e] = Al[n[k] + s <= M.C ? i + static_cast<uint32_t>(s) * st : occ];
-      }
-    }
-    const double idle = M.mu_L * static_cast<double>(M.KC - load);
-    double anew = 0.0;
-#pragma unroll
-    for (int e = 0; e < J; ++e) {
-      double ab = aa[0][e];
-#pragma unroll
-      for (int a = 1; a < K; ++a) ab = fmax(ab, aa[a][e]);
-      double D = idle * static_cast<double>(vs[e]);
-      double rs = 0.0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        D = fma(M.mu_L * n[k], static_cast<double>(vd[k][e]), D);
-        rs += static_cast<double>(vr[k][e]);
-      }
-      D = fma(M.nu_L, rs, D);
-      const double best = fmax(fma(M.gamma, a_rej, M.r_reject[e]), fma(M.gamma, ab, M.r_place[e]));
-      const float vn = static_cast<float>(fma(M.gamma, D, best));
-      st_f32(vout, vn, i4, o0 * 4u + e * cls);
-      anew = fma(M.p[e], static_cast<double>(vn), anew);
-      const double dd = fabs(static_cast<double>(vn) - static_cast<double>(vs[e]));
-      dmax = fmax(dmax, dd);
-      bad = bad || (dd != dd);
-    }
-    st_f64(aout, anew, i8, o0 * 8u);
-  }
-  __syncthreads();   // the next tile overwrites the LDS image
+    __syncthreads();   // the next tile overwrites the LDS image
   }
   block_max_to(bad ? NAN : dmax, ctl, res, j, tol);
 }
 
-bool vi_tile_shape(const Model& M, TileShape* S) { return tile_shape(M, 4u * M.J + 8u, S); }
+template <int K, int J, int T>
+__global__ __launch_bounds__(kBlock) void vi_bsdi_kernel(Model M, TileShape S, int inner,
+                                                          const float* __restrict__ Vin, float* __restrict__ Vout,
+                                                          const double* __restrict__ Ain,
+                                                          double* __restrict__ Aout, Ctl* ctl, double* res,
+                                                          long long j, double tol) {
+  if (sweep_stopped<ResKind::kMax>(ctl, res, j, tol)) return;
+  extern __shared__ double tile_lds[];
+  const uint32_t occ = S.occ;
+  // two LDS images: episode k reads image k % 2 and writes the other
+  const uint32_t img = occ + 1 + (occ * J + 1) / 2;   // doubles per image
+  double* Al[2] = {tile_lds, tile_lds + img};
+  float* Vl[2] = {reinterpret_cast<float*>(Al[0] + occ + 1), reinterpret_cast<float*>(Al[1] + occ + 1)};
+  const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
+  const uint32_t ns = static_cast<uint32_t>(M.n_states);
+  const uint32_t cls = nocc * 4u;
+  const BufView vin = make_view(Vin, ns * 4u);
+  const BufView vout = make_view(Vout, ns * 4u);
+  const BufView ain = make_view(Ain, (nocc + kSentinel) * 8u);
+  const BufView aout = make_view(Aout, nocc * 8u);
+  double dmax = 0.0;
+  bool bad = false;
+  const TileWalk tw = tile_walk(S);
+  for (uint32_t tb = tw.first; tb < tw.end; tb += tw.step) {
+    TileHigh<K, J, T> H;
+    tile_high_setup<K, J, T>(M, tb, H);
+    tile_stage<J>(M, occ, H.o0, vin, ain, Vl[0], Al[0]);
+    if (threadIdx.x == 0) Al[1][occ] = -INFINITY;
+    __syncthreads();
+    for (int k = 0; k < inner; ++k) {
+      const int src = k & 1;
+      const bool last = k + 1 == inner;
+      for (uint32_t i = threadIdx.x; i < occ; i += kBlock) {
+        float vs[J], vn[J];
+        double anew;
+        tile_backup<K, J, T, true>(M, H, occ, Vl[src], Al[src], vin, ain, i, vs, vn, anew);
+        if (!last) {
+#pragma unroll
+          for (int e = 0; e < J; ++e) Vl[src ^ 1][e * occ + i] = vn[e];
+          Al[src ^ 1][i] = anew;
+        } else {
+#pragma unroll
+          for (int e = 0; e < J; ++e) {
+            st_f32(vout, vn[e], i * 4u, H.o0 * 4u + e * cls);
+            // change against the previous pass, whose value was staged
+            const float v0 = k == 0 ? vs[e] : ld_f32(vin, i * 4u, H.o0 * 4u + e * cls);
+            const double dd = fabs(static_cast<double>(vn[e]) - static_cast<double>(v0));
+            dmax = fmax(dmax, dd);
+            bad = bad || (dd != dd);
+          }
+          st_f64(aout, anew, i * 8u, H.o0 * 8u);
+        }
+      }
+      __syncthreads();   // episode k's image is complete before episode k+1 reads it
+    }
+  }
+  block_max_to(bad ? NAN : dmax, ctl, res, j, tol);
+}
+
+bool vi_tile_shape(const Model& M, TileShape* S) { return tile_shape(M, 4u * M.J + 8u, kTileLds, S); }
+
+bool vi_bsdi_shape(const Model& M, TileShape* S) {
+  return tile_shape(M, 2u * (4u * M.J + 8u), kBsdiLds, S);
+}
 
 hipError_t launch_vi_tile(const Model& M, const TileShape& S, const float* Vin, float* Vout, const double* Ain,
                           double* Aout, Ctl* ctl, double* res, long long j, double tol, hipStream_t s) {
@@ -138,6 +263,19 @@ hipError_t launch_vi_tile(const Model& M, const TileShape& S, const float* Vin, 
     constexpr int Kc = decltype(kc)::value, Jc = decltype(jc)::value, Tc = decltype(tc)::value;
     hipLaunchKernelGGL((vi_tile_kernel<Kc, Jc, Tc>), dim3(S.grid), dim3(kBlock), lds, s, M, S, Vin, Vout, Ain,
                        Aout, ctl, res, j, tol);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_vi_bsdi(const Model& M, const TileShape& S, int inner, const float* Vin, float* Vout,
+                          const double* Ain, double* Aout, Ctl* ctl, double* res, long long j, double tol,
+                          hipStream_t s) {
+  const size_t img = static_cast<size_t>(S.occ) + 1 + (static_cast<size_t>(S.occ) * M.J + 1) / 2;
+  const size_t lds = 2 * img * 8;
+  return tile_dispatch(M.K, M.J, S.T, [&](auto kc, auto jc, auto tc) {
+    constexpr int Kc = decltype(kc)::value, Jc = decltype(jc)::value, Tc = decltype(tc)::value;
+    hipLaunchKernelGGL((vi_bsdi_kernel<Kc, Jc, Tc>), dim3(S.grid), dim3(kBlock), lds, s, M, S, inner, Vin,
+                       Vout, Ain, Aout, ctl, res, j, tol);
     return hipGetLastError();
   });
 }
