@@ -107,6 +107,18 @@ def bsdi_comparison(mdp, N: int, tol: float, inners=(1, 2, 4, 8)) -> dict:
     return out
 
 
+def policy_iteration_run(mdp, eval_tol: float) -> dict:
+    """Howard's policy iteration from the least-loaded heuristic."""
+    import torch
+    pi = mdp.policy_greedy("least_loaded")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pi, V, st, rounds = mdp.policy_iteration(pi, eval_tol=eval_tol, improve_tol=1e-7)
+    torch.cuda.synchronize()
+    return {"start": "least-loaded heuristic", "rounds": rounds, "eval_sweeps": st["iterations"],
+            "seconds": time.perf_counter() - t0, "eval_tol": eval_tol, "improve_tol": 1e-7}
+
+
 def _sub_solution(p):
     """A constant sub-solution of the Bellman operator: the least one-step
     reward over the discount horizon (value iteration from it is monotone)."""
@@ -312,6 +324,7 @@ def main() -> int:
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
+    pi_run = policy_iteration_run(mdp, args.eval_tol)
     bsdi = None
     if args.bsdi:
         try:
@@ -409,6 +422,7 @@ def main() -> int:
         "roofline": roof,
         "kernels": kernels,
         "bsdi_vs_jacobi": bsdi,
+        "policy_iteration": pi_run,
     }
     del Vh
     if args.batch:

@@ -217,6 +217,31 @@ int vi_solve_batch(mdpvi_batch_t b, float *V, double tol, int64_t max_iter,
                    void *hip_stream, mdpvi_stats *st, int64_t *iterations,
                    double *residuals);
 
+/* Policy iteration (Howard's, with full evaluations): repeat { evaluate pi
+ * in FP64 (policy_eval to eval_tol, at most eval_max_iter sweeps); improve:
+ * pi'(s) = pi(s) unless some action's FP64 Q (formed from V_pi as in
+ * policy_extract_f64) exceeds Q(s, pi(s)) by more than improve_tol, else
+ * the lowest-index argmax } until pi' = pi.  Keeping the current action on
+ * near-ties stops the cycling between equivalent hosts that rounding would
+ * otherwise cause; at the end pi is improve_tol-greedy for its own value,
+ * so V* - V_pi <= (improve_tol + 2 gamma bound)/(1 - gamma) elementwise, with
+ * bound the last evaluation's error bound (st->bound_inf).  Choose
+ * improve_tol above twice that bound.
+ * pi: device uint8[N], in the starting policy (every action feasible), out
+ * the final policy; V: device double[N], in the first evaluation's starting
+ * iterate, out V_pi of the final policy (each evaluation starts from the
+ * previous one's result).  rounds (host, nullable): evaluations done.
+ * st: evaluation sweeps summed (iterations, backups, bytes, sweep_seconds),
+ * the last evaluation's residual and bound, host wall seconds of the call.
+ * Synchronous.  Errors: MDPVI_EINVAL (NULL pointer, eval_tol <= 0,
+ * improve_tol < 0 or not finite, eval_max_iter or max_rounds < 1, an
+ * infeasible action in pi); MDPVI_ENOCONV if an evaluation reaches
+ * eval_max_iter or the policy still changes after max_rounds (pi and V hold
+ * the last round's); MDPVI_ENAN, MDPVI_EDEVICE, MDPVI_ENOMEM.               */
+int policy_iteration(mdpvi_mdp_t h, uint8_t *pi, double *V, double eval_tol, int64_t eval_max_iter,
+                     double improve_tol, int64_t max_rounds, void *hip_stream, mdpvi_stats *st,
+                     int64_t *rounds);
+
 /* Block-asynchronous value iteration (the paper's BSDI, Alg. 4) on the tiles
  * of the tile form: a pass stages each tile of (C+1)^T occupancies (all
  * classes) in LDS and runs `inner` synchronous episodes of the Bellman backup

@@ -92,6 +92,8 @@ SIGNATURES = {
     "mdp_set_timing": (ctypes.c_int, [_vp, _c_int32]),
     "mdp_set_sweep_form": (ctypes.c_int, [_vp, _c_int32]),
     "vi_solve_bsdi": (ctypes.c_int, [_vp, _vp, _c_double, _c_int64, _c_int32, _vp, ctypes.POINTER(Stats)]),
+    "policy_iteration": (ctypes.c_int, [_vp, _vp, _vp, _c_double, _c_int64, _c_double, _c_int64, _vp,
+                                        ctypes.POINTER(Stats), ctypes.POINTER(_c_int64)]),
     "mdp_sweep_forms": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32)]),
     "mdp_autotune": (ctypes.c_int, [_vp, _vp, _c_int32, _vp, ctypes.POINTER(_c_int32),
                                     ctypes.POINTER(_c_double)]),
@@ -272,6 +274,23 @@ class MDP:
                                   _dev_tensor(V, torch.float64, n, "V"), float(tol),
                                   int(max_iter), _stream_ptr(stream), ctypes.byref(st)), st)
         return V, st.as_dict()
+
+    def policy_iteration(self, pi, V=None, eval_tol: float = 1e-10, eval_max_iter: int = 10_000_000,
+                         improve_tol: float = 1e-7, max_rounds: int = 100, stream=None):
+        """Howard's policy iteration from pi (updated in place); returns
+        (pi, V_pi, stats, rounds)."""
+        import torch
+        n = self.num_states
+        if V is None:
+            V = torch.zeros(n, dtype=torch.float64, device=pi.device)
+        st = Stats()
+        r = _c_int64()
+        _check(load().policy_iteration(self._h, _dev_tensor(pi, torch.uint8, n, "pi"),
+                                       _dev_tensor(V, torch.float64, n, "V"), float(eval_tol),
+                                       int(eval_max_iter), float(improve_tol), int(max_rounds),
+                                       _stream_ptr(stream),
+                                       ctypes.byref(st), ctypes.byref(r)), st)
+        return pi, V, st.as_dict(), r.value
 
     def policy_greedy(self, kind: str = "least_loaded", pi=None, stream=None):
         import torch

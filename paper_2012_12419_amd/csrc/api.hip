@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <fstream>
 #include <map>
+#include <chrono>
 #include <mutex>
 #include <new>
 #include <sstream>
@@ -35,6 +36,7 @@ struct mdpvi_mdp {
   int device = -1;              // device of the scratch below (-1: none yet)
   void* vbuf = nullptr;         // second value buffer (ping-pong partner)
   size_t vbuf_bytes = 0;
+  uint8_t* pbuf = nullptr;      // policy scratch (policy iteration), N + 16 bytes
   double* abuf = nullptr;       // two FP64 arrival-term arrays of n_occ + kSentinel doubles
                                 // (exact-shape direct and tile forms)
   Ctl* ctl = nullptr;           // device control words
@@ -228,6 +230,9 @@ int eval_form(mdpvi_mdp* h, mdpvi::TileShape* S) {
   mdpvi::tile_set_walkers(S, w, cu_count());
   return MDPVI_FORM_TILE + w;
 }
+
+int eval_run(mdpvi_mdp* h, const uint8_t* pi, double* V, double tol, int64_t max_iter, hipStream_t s,
+             mdpvi_stats* st);
 
 double bits_to_double(unsigned long long b) {
   double d;
@@ -552,6 +557,7 @@ void mdp_free(mdpvi_mdp_t h) {
   if (!h) return;
   if (h->vbuf) (void)hipFree(h->vbuf);
   if (h->abuf) (void)hipFree(h->abuf);
+  if (h->pbuf) (void)hipFree(h->pbuf);
   if (h->ctl) (void)hipFree(h->ctl);
   if (h->ctl_host) (void)hipHostFree(h->ctl_host);
   if (h->res) (void)hipFree(h->res);
@@ -761,6 +767,18 @@ int policy_eval(mdpvi_mdp_t h, const uint8_t* pi, double* V, double tol, int64_t
   HIP_TRY(hipStreamSynchronize(s));
   if (h->ctl_host->flag)
     return fail(MDPVI_EINVAL, "policy has an action that is not feasible in its state");
+  return eval_run(h, pi, V, tol, max_iter, s, st);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Evaluation sweeps of a policy known to be feasible (policy_eval after its
+// check; policy_iteration).  The scratch must hold N doubles.
+int eval_run(mdpvi_mdp* h, const uint8_t* pi, double* V, double tol, int64_t max_iter, hipStream_t s,
+             mdpvi_stats* st) {
+  const Model& M = h->M;
   // the tile form where it applies and is worthwhile, or where the handle
   // asks for it; the direct form otherwise
   mdpvi::TileShape S{};
@@ -786,6 +804,72 @@ int policy_eval(mdpvi_mdp_t h, const uint8_t* pi, double* V, double tol, int64_t
                             return mdpvi::launch_eval_sweep(M, pi, in, out, h->ctl, h->res, j, tol, s);
                           },
                           false, mdpvi::eval_sweep_grid(M));
+}
+
+}  // namespace
+
+extern "C" {
+
+int policy_iteration(mdpvi_mdp_t h, uint8_t* pi, double* V, double eval_tol, int64_t eval_max_iter,
+                     double improve_tol, int64_t max_rounds, void* hip_stream, mdpvi_stats* st,
+                     int64_t* rounds) {
+  if (!h || !V || !pi) return fail(MDPVI_EINVAL, "NULL handle, policy or value array");
+  if (!(eval_tol > 0)) return fail(MDPVI_EINVAL, "eval_tol=%g must be > 0", eval_tol);
+  if (!(improve_tol >= 0) || std::isinf(improve_tol))
+    return fail(MDPVI_EINVAL, "improve_tol=%g must be finite and >= 0", improve_tol);
+  if (eval_max_iter < 1 || max_rounds < 1)
+    return fail(MDPVI_EINVAL, "eval_max_iter=%lld and max_rounds=%lld must be >= 1", (long long)eval_max_iter,
+                (long long)max_rounds);
+  const Model& M = h->M;
+  const size_t N = static_cast<size_t>(M.n_states);
+  int rc = ensure_scratch(h, N * sizeof(double));
+  if (rc) return rc;
+  if (!h->pbuf) {
+    if (hipMalloc(reinterpret_cast<void**>(&h->pbuf), N + 16) != hipSuccess) {
+      h->pbuf = nullptr;
+      return fail(MDPVI_ENOMEM, "hipMalloc of the policy scratch failed");
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));
+  HIP_TRY(mdpvi::launch_policy_check(M, pi, h->ctl, s));
+  HIP_TRY(hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h->ctl_host->flag)
+    return fail(MDPVI_EINVAL, "policy has an action that is not feasible in its state");
+  const auto t0 = std::chrono::steady_clock::now();
+  mdpvi_stats tot{};
+  int64_t r = 0;
+  bool stable = false;
+  while (r < max_rounds && !stable) {
+    ++r;
+    mdpvi_stats e{};
+    rc = eval_run(h, pi, V, eval_tol, eval_max_iter, s, &e);
+    tot.iterations += e.iterations;
+    tot.residual_inf = e.residual_inf;
+    tot.bound_inf = e.bound_inf;
+    tot.backups += e.backups;
+    tot.bytes += e.bytes;
+    tot.sweep_seconds += e.sweep_seconds;
+    if (rc != MDPVI_OK) break;
+    // improvement: keep the current action unless another beats its Q by
+    // more than improve_tol (lowest-index argmax then), FP64
+    HIP_TRY(mdpvi::launch_improve(M, V, pi, h->pbuf, improve_tol, s));
+    HIP_TRY(mdpvi::launch_ctl_init(h->ctl, nullptr, s));
+    HIP_TRY(mdpvi::launch_policy_diff(N, pi, h->pbuf, h->ctl, s));
+    HIP_TRY(hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    stable = h->ctl_host->flag == 0;
+    if (!stable) HIP_TRY(hipMemcpyAsync(pi, h->pbuf, N, hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  tot.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st) *st = tot;
+  if (rounds) *rounds = r;
+  if (rc != MDPVI_OK) return rc;
+  if (!stable)
+    return fail(MDPVI_ENOCONV, "policy still changing after %lld rounds (max_rounds)", (long long)r);
+  return MDPVI_OK;
 }
 
 int vi_adjoint(mdpvi_mdp_t h, const uint8_t* pi, const double* V_pi, float* w, double* grad,

@@ -65,6 +65,12 @@ hipError_t launch_extract_f64(const Model& M, const double* V, uint8_t* pi, floa
 
 // ctl->flag := 1 if some pi entry is not a feasible action.
 hipError_t launch_policy_check(const Model& M, const uint8_t* pi, Ctl* ctl, hipStream_t s);
+// Policy improvement: pi_out = pi_in where no action beats the current one's
+// FP64 Q (from V) by more than tol, the lowest-index argmax elsewhere.
+hipError_t launch_improve(const Model& M, const double* V, const uint8_t* pi_in, uint8_t* pi_out, double tol,
+                          hipStream_t s);
+// ctl->flag := 1 if the n-byte arrays a and b differ.
+hipError_t launch_policy_diff(uint64_t n, const uint8_t* a, const uint8_t* b, Ctl* ctl, hipStream_t s);
 
 // One fixed-policy FP64 sweep V^{j+1} = r_pi + gamma P_pi V^j.
 hipError_t launch_eval_sweep(const Model& M, const uint8_t* pi, const double* Vin, double* Vout,

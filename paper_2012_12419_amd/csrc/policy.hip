@@ -203,6 +203,54 @@ hipError_t launch_policy_check(const Model& M, const uint8_t* pi, Ctl* ctl, hipS
   return hipGetLastError();
 }
 
+template <int KMAX, int JMAX, typename Idx>
+__global__ __launch_bounds__(kBlock) void improve_kernel(Model M, const double* __restrict__ V,
+                                                          const uint8_t* __restrict__ pi_in,
+                                                          uint8_t* __restrict__ pi_out, double tol) {
+  const Idx o = static_cast<Idx>(blockIdx.x) * kBlock + threadIdx.x;
+  if (o < static_cast<Idx>(M.n_occ)) improve_occupancy<KMAX, JMAX>(M, V, pi_in, pi_out, tol, o);
+}
+
+hipError_t launch_improve(const Model& M, const double* V, const uint8_t* pi_in, uint8_t* pi_out, double tol,
+                          hipStream_t s) {
+  return dispatch_kj(M, [&](auto km, auto jm) {
+    constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
+    if (use_32bit_index(M))
+      hipLaunchKernelGGL((improve_kernel<KM, JM, uint32_t>), occ_grid(M), dim3(kBlock), 0, s, M, V, pi_in,
+                         pi_out, tol);
+    else
+      hipLaunchKernelGGL((improve_kernel<KM, JM, uint64_t>), occ_grid(M), dim3(kBlock), 0, s, M, V, pi_in,
+                         pi_out, tol);
+    return hipGetLastError();
+  });
+}
+
+// ctl->flag := 1 if the byte arrays a and b (n bytes) differ anywhere.
+// Sixteen bytes per thread (one 16-byte load each when both arrays are
+// 16-byte aligned); one store per wavefront that found a difference.
+__global__ __launch_bounds__(kBlock) void policy_diff_kernel(uint64_t n, const uint8_t* __restrict__ a,
+                                                              const uint8_t* __restrict__ b, Ctl* ctl) {
+  const uint64_t i = (static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x) * 16u;
+  bool diff = false;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15u) == 0;
+  if (aligned && i + 16u <= n) {
+    const uint4 x = *reinterpret_cast<const uint4*>(a + i);
+    const uint4 y = *reinterpret_cast<const uint4*>(b + i);
+    diff = (x.x != y.x) || (x.y != y.y) || (x.z != y.z) || (x.w != y.w);
+  } else {
+    for (uint64_t k = i; k < n && k < i + 16u; ++k) diff = diff || (a[k] != b[k]);
+  }
+  if (__ballot(diff) != 0 && threadIdx.x % kWave == 0) ctl->flag = 1;
+}
+
+hipError_t launch_policy_diff(uint64_t n, const uint8_t* a, const uint8_t* b, Ctl* ctl, hipStream_t s) {
+  const uint64_t threads = (n + 15) / 16;
+  const uint32_t grid = static_cast<uint32_t>((threads + kBlock - 1) / kBlock);
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(policy_diff_kernel, dim3(grid), dim3(kBlock), 0, s, n, a, b, ctl);
+  return hipGetLastError();
+}
+
 hipError_t launch_eval_sweep(const Model& M, const uint8_t* pi, const double* Vin, double* Vout,
                              Ctl* ctl, double* res, long long j, double tol, hipStream_t s) {
   if (eval_exact_shape(M)) return launch_eval_exact(M, pi, Vin, Vout, ctl, res, j, tol, s);

@@ -87,6 +87,52 @@ __device__ __forceinline__ void extract_occupancy(const Model& M, const T* __res
   }
 }
 
+// Policy improvement at occupancy o (all classes), Q formed in FP64 from V
+// as in extract_occupancy: the current action pi_in stays unless some action
+// beats its Q by more than tol; then the lowest-index argmax.
+template <int KMAX, int JMAX, typename Idx>
+__device__ __forceinline__ void improve_occupancy(const Model& M, const double* __restrict__ V,
+                                                  const uint8_t* __restrict__ pi_in, uint8_t* __restrict__ pi_out,
+                                                  double tol, Idx o) {
+  const Idx nocc = static_cast<Idx>(M.n_occ);
+  int n[KMAX];
+  decode<KMAX>(M, o, n);
+  int load = 0;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) load += n[k];
+  const double a_rej = arrival<JMAX>(M, V, o, nocc);
+#pragma unroll
+  for (int e = 0; e < JMAX; ++e) {
+    if (e < M.J) {
+      const Idx base = o + e * nocc;
+      const double D = no_arrival<KMAX>(M, V, base, n, load);
+      const int se = M.size[e];
+      const int cur = pi_in[base];
+      double best = 0.0, q_cur = 0.0;
+      int arg = -1;
+#pragma unroll
+      for (int a = 0; a <= KMAX; ++a) {
+        if (a <= M.K) {
+          double q;
+          if (a < M.K) {
+            if (n[a] + se > M.C) continue;
+            const Idx m = o + static_cast<Idx>(se) * static_cast<Idx>(M.stride[a]);
+            q = fma(M.gamma, arrival<JMAX>(M, V, m, nocc) + D, M.r_place[e]);
+          } else {
+            q = fma(M.gamma, a_rej + D, M.r_reject[e]);
+          }
+          if (a == cur) q_cur = q;
+          if (arg < 0 || q > best) {
+            best = q;
+            arg = a;
+          }
+        }
+      }
+      pi_out[base] = static_cast<uint8_t>(q_cur >= best - tol ? cur : arg);
+    }
+  }
+}
+
 // True if some class at occupancy o has an action that is not feasible.
 template <int KMAX, int JMAX, typename Idx>
 __device__ __forceinline__ bool check_occupancy(const Model& M, const uint8_t* __restrict__ pi, Idx o) {
