@@ -125,7 +125,8 @@ def _sub_solution(p):
     import numpy as np
     lam = np.asarray(p.lam)
     Lam = lam.sum() + p.K * p.C * p.mu + p.K * p.nu
-    return -lam.sum() / Lam * max(p.reject_cost) / (1 - p.gamma)
+    worst = lam.sum() / Lam * max(p.reject_cost) + p.idle_unit_cost * p.K * p.C
+    return -worst / (1 - p.gamma)
 
 
 def gradient_workloads(mdpvi, n_batch: int, tol: float) -> dict:

@@ -66,7 +66,11 @@ extern "C" {
  *   K in [1, 16], C >= 1, J in [1, 8], 1 <= size[j] <= C,
  *   lambda[j] >= 0 finite with sum > 0, mu >= 0, nu >= 0 finite,
  *   reward[j] finite, reject_cost NULL (all 0) or finite entries,
- *   gamma in [0, 1).                                                      */
+ *   gamma in [0, 1), idle_unit_cost >= 0 finite.
+ * One uniformised step from (n, e) earns P_arr R(e, a) - idle_unit_cost
+ * (KC - sum_k n_k): the placement reward r_e or the paid-cloud cost -c_e on
+ * the arrival branch, less the under-utilisation penalty of Eq. (16) on
+ * every free VM unit of every host (0 by default).                         */
 typedef struct {
     int32_t K, C, J;
     const int32_t *size;
@@ -76,6 +80,7 @@ typedef struct {
     const double *reward;
     const double *reject_cost;
     double gamma;
+    double idle_unit_cost;
 } mdpvi_params;
 
 typedef struct mdpvi_mdp *mdpvi_mdp_t;

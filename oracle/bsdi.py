@@ -53,18 +53,19 @@ def backup_mixed(p, g: Grid, Vcur: np.ndarray, Vold: np.ndarray, T: int) -> np.n
         else:
             D += (p.nu / Lam) * np.where((nk == 0)[None, :], Vc[:, reset], Vo[:, reset])
     # Q of every action, then the max (vi.q_table's layout and order)
+    hold = p.idle_unit_cost * (p.K * p.C - g.load)
     N = p.J * g.n_occ
     Q = np.full((N, p.K + 1), NEG_INF)
     for e in range(p.J):
         rows = slice(e * g.n_occ, (e + 1) * g.n_occ)
         s = p.size[e]
-        Q[rows, p.K] = -P_arr * p.reject_cost[e] + p.gamma * (A_cur + D[e])
+        Q[rows, p.K] = -P_arr * p.reject_cost[e] - hold + p.gamma * (A_cur + D[e])
         for a in range(p.K):
             room = g.digits[:, a] + s <= p.C
             m = occ[room] + s * g.stride[a]
             A = A_cur if a < T else A_old
             q = np.full(g.n_occ, NEG_INF)
-            q[room] = P_arr * p.reward[e] + p.gamma * (A[m] + D[e][room])
+            q[room] = P_arr * p.reward[e] - hold[room] + p.gamma * (A[m] + D[e][room])
             Q[rows, a] = q
     return Q.max(axis=1)
 

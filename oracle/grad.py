@@ -66,7 +66,8 @@ def _edges(p, pi: np.ndarray, theta: torch.Tensor, g: vi.Grid):
         m = occ.copy()
         m[place] += se * g.stride[a[place]]
         place_t = torch.from_numpy(place)
-        r_parts.append(torch.where(place_t, P_arr * rew[e], -P_arr * cost[e]))
+        r_parts.append(torch.where(place_t, P_arr * rew[e], -P_arr * cost[e])
+                       - p.idle_unit_cost * (p.K * p.C - load))
         for j in range(J):
             rows.append(src); cols.append(m + j * g.n_occ)
             vals.append((lam[j] / Lam).expand(g.n_occ))

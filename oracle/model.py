@@ -102,13 +102,16 @@ def uniformisation_rate(p, exact: bool = False):
 
 
 def reward(p, s: int, a: int, exact: bool = False):
-    """Expected one-step reward P_arr * R(e, a) (Sec. V-E, Eqs. (14)-(16))."""
+    """Expected one-step reward P_arr * R(e, a) (Sec. V-E, Eqs. (14)-(16)),
+    less the under-utilisation penalty of Eq. (16) on every free VM unit:
+    idle_unit_cost * (K C - sum_k n_k)."""
     n, e = decode(p, s)
     F = Fraction if exact else float
     lam_tot = sum(F(x) for x in p.lam)
     Lam = uniformisation_rate(p, exact)
     R = F(p.reward[e]) if a < p.K else -F(p.reject_cost[e])
-    return lam_tot / Lam * R
+    free = p.K * p.C - sum(n)
+    return lam_tot / Lam * R - F(p.idle_unit_cost) * free
 
 
 def transitions(p, s: int, a: int, exact: bool = False) -> Dict[int, object]:

@@ -80,14 +80,15 @@ def q_table(p, V: np.ndarray, g: Optional[Grid] = None) -> np.ndarray:
     lam, Lam, P_arr = rates(p)
     A, D = _branch_terms(p, g, np.asarray(V, dtype=np.float64))
     occ = np.arange(g.n_occ, dtype=np.int64)
+    hold = p.idle_unit_cost * (p.K * p.C - g.load)   # under-utilisation penalty, Eq. (16)
     Q = np.full((p.J, g.n_occ, p.K + 1), NEG_INF)
     for e in range(p.J):
         se = p.size[e]
         for a in range(p.K):
             feas = g.digits[:, a] + se <= p.C
             m = occ[feas] + se * g.stride[a]
-            Q[e, feas, a] = P_arr * p.reward[e] + p.gamma * (A[m] + D[e, feas])
-        Q[e, :, p.K] = -P_arr * p.reject_cost[e] + p.gamma * (A + D[e])
+            Q[e, feas, a] = P_arr * p.reward[e] - hold[feas] + p.gamma * (A[m] + D[e, feas])
+        Q[e, :, p.K] = -P_arr * p.reject_cost[e] - hold + p.gamma * (A + D[e])
     return Q.reshape(p.J * g.n_occ, p.K + 1)
 
 
@@ -180,7 +181,8 @@ def policy_system(p, pi: np.ndarray, g: Optional[Grid] = None):
                 raise ValueError("policy chooses an infeasible placement")
         m = occ.copy()
         m[place] += se * g.stride[a[place]]
-        r[e] = np.where(place, P_arr * p.reward[e], -P_arr * p.reject_cost[e])
+        r[e] = (np.where(place, P_arr * p.reward[e], -P_arr * p.reject_cost[e])
+                - p.idle_unit_cost * (p.K * p.C - g.load))
         for j in range(p.J):
             rows.append(src); cols.append(m + j * g.n_occ)
             vals.append(np.full(g.n_occ, lam[j] / Lam))

@@ -46,7 +46,7 @@ class Params(ctypes.Structure):
                 ("size", ctypes.POINTER(_c_int32)), ("lam", ctypes.POINTER(_c_double)),
                 ("mu", _c_double), ("nu", _c_double),
                 ("reward", ctypes.POINTER(_c_double)), ("reject_cost", ctypes.POINTER(_c_double)),
-                ("gamma", _c_double)]
+                ("gamma", _c_double), ("idle_unit_cost", _c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -155,7 +155,7 @@ def _dev_tensor(t, dtype, n: int, name: str):
 
 def make_params(K: int, C: int, size: Sequence[int], lam: Sequence[float], mu: float, nu: float,
                 reward: Sequence[float], gamma: float,
-                reject_cost: Optional[Sequence[float]] = None):
+                reject_cost: Optional[Sequence[float]] = None, idle_unit_cost: float = 0.0):
     """ctypes Params plus the arrays it points into (keep both alive)."""
     J = len(size)
     keep = [(_c_int32 * J)(*[int(s) for s in size]), (_c_double * J)(*[float(x) for x in lam]),
@@ -163,7 +163,8 @@ def make_params(K: int, C: int, size: Sequence[int], lam: Sequence[float], mu: f
     rc = (_c_double * J)(*[float(x) for x in reject_cost]) if reject_cost is not None else None
     keep.append(rc)
     p = Params(int(K), int(C), J, keep[0], keep[1], float(mu), float(nu), keep[2],
-               ctypes.cast(rc, ctypes.POINTER(_c_double)) if rc is not None else None, float(gamma))
+               ctypes.cast(rc, ctypes.POINTER(_c_double)) if rc is not None else None, float(gamma),
+               float(idle_unit_cost))
     return p, keep
 
 
@@ -172,9 +173,9 @@ class MDP:
 
     def __init__(self, K: int, C: int, size: Sequence[int], lam: Sequence[float], mu: float,
                  nu: float, reward: Sequence[float], gamma: float,
-                 reject_cost: Optional[Sequence[float]] = None):
+                 reject_cost: Optional[Sequence[float]] = None, idle_unit_cost: float = 0.0):
         lib = load()
-        p, keep = make_params(K, C, size, lam, mu, nu, reward, gamma, reject_cost)
+        p, keep = make_params(K, C, size, lam, mu, nu, reward, gamma, reject_cost, idle_unit_cost)
         h = ctypes.c_void_p()
         _check(lib.mdp_build(ctypes.byref(p), ctypes.byref(h)))
         self._h = h
@@ -188,7 +189,7 @@ class MDP:
     @classmethod
     def from_instance(cls, inst) -> "MDP":
         return cls(inst.K, inst.C, inst.size, inst.lam, inst.mu, inst.nu, inst.reward,
-                   inst.gamma, inst.reject_cost)
+                   inst.gamma, inst.reject_cost, getattr(inst, "idle_unit_cost", 0.0))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -336,7 +337,8 @@ class Batch:
         arr = (Params * len(instances))()
         for i, inst in enumerate(instances):
             prm, keep = make_params(inst.K, inst.C, inst.size, inst.lam, inst.mu, inst.nu,
-                                    inst.reward, inst.gamma, inst.reject_cost)
+                                    inst.reward, inst.gamma, inst.reject_cost,
+                                    getattr(inst, "idle_unit_cost", 0.0))
             arr[i] = prm
             self._keep.append(keep)
         h = ctypes.c_void_p()

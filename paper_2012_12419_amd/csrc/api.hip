@@ -425,6 +425,8 @@ int fill_model(const mdpvi_params* p, Model& M, int64_t& pairs_out) {
   if (!(p->gamma >= 0.0 && p->gamma < 1.0)) return fail(MDPVI_EINVAL, "gamma=%g outside [0, 1)", p->gamma);
   if (!is_finite(p->mu) || p->mu < 0) return fail(MDPVI_EINVAL, "mu=%g must be finite and >= 0", p->mu);
   if (!is_finite(p->nu) || p->nu < 0) return fail(MDPVI_EINVAL, "nu=%g must be finite and >= 0", p->nu);
+  if (!is_finite(p->idle_unit_cost) || p->idle_unit_cost < 0)
+    return fail(MDPVI_EINVAL, "idle_unit_cost=%g must be finite and >= 0", p->idle_unit_cost);
   double lam_tot = 0.0;
   for (int j = 0; j < p->J; ++j) {
     if (p->size[j] < 1 || p->size[j] > p->C)
@@ -476,6 +478,7 @@ int fill_model(const mdpvi_params* p, Model& M, int64_t& pairs_out) {
   }
   M.mu_L = p->mu / Lam;
   M.nu_L = p->nu / Lam;
+  M.hold = p->idle_unit_cost;
   M.gamma = p->gamma;
   for (int j = 0; j < p->J; ++j) {
     M.lam[j] = p->lambda[j];

@@ -73,6 +73,7 @@ struct Model {
   double nu_L;                  // nu / Lam
   double r_place[kMaxJ];        // P_arr * reward_j
   double r_reject[kMaxJ];       // -P_arr * reject_cost_j
+  double hold;                  // under-utilisation penalty per free unit and step
   double gamma;
   // raw parameters, for the gradient with respect to them
   double lam[kMaxJ];            // lambda_j

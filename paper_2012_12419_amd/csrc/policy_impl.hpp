@@ -47,6 +47,7 @@ __device__ __forceinline__ void extract_occupancy(const Model& M, const T* __res
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) load += n[k];
   const double a_rej = arrival<JMAX>(M, V, o, nocc);
+  const double fu = static_cast<double>(M.KC - load);   // free units (under-utilisation penalty)
 #pragma unroll
   for (int e = 0; e < JMAX; ++e) {
     if (e < M.J) {
@@ -63,9 +64,9 @@ __device__ __forceinline__ void extract_occupancy(const Model& M, const T* __res
           if (a < M.K) {
             if (n[a] + se > M.C) continue;
             const Idx m = o + static_cast<Idx>(se) * static_cast<Idx>(M.stride[a]);
-            q = fma(M.gamma, arrival<JMAX>(M, V, m, nocc) + D, M.r_place[e]);
+            q = fma(M.gamma, arrival<JMAX>(M, V, m, nocc) + D, fma(-M.hold, fu, M.r_place[e]));
           } else {
-            q = fma(M.gamma, a_rej + D, M.r_reject[e]);
+            q = fma(M.gamma, a_rej + D, fma(-M.hold, fu, M.r_reject[e]));
           }
           if (arg < 0) {
             best = q;
@@ -101,6 +102,7 @@ __device__ __forceinline__ void improve_occupancy(const Model& M, const double* 
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) load += n[k];
   const double a_rej = arrival<JMAX>(M, V, o, nocc);
+  const double fu = static_cast<double>(M.KC - load);   // free units (under-utilisation penalty)
 #pragma unroll
   for (int e = 0; e < JMAX; ++e) {
     if (e < M.J) {
@@ -117,9 +119,9 @@ __device__ __forceinline__ void improve_occupancy(const Model& M, const double* 
           if (a < M.K) {
             if (n[a] + se > M.C) continue;
             const Idx m = o + static_cast<Idx>(se) * static_cast<Idx>(M.stride[a]);
-            q = fma(M.gamma, arrival<JMAX>(M, V, m, nocc) + D, M.r_place[e]);
+            q = fma(M.gamma, arrival<JMAX>(M, V, m, nocc) + D, fma(-M.hold, fu, M.r_place[e]));
           } else {
-            q = fma(M.gamma, a_rej + D, M.r_reject[e]);
+            q = fma(M.gamma, a_rej + D, fma(-M.hold, fu, M.r_reject[e]));
           }
           if (a == cur) q_cur = q;
           if (arg < 0 || q > best) {
@@ -188,7 +190,7 @@ __device__ __forceinline__ double eval_occupancy(const Model& M, const uint8_t* 
       }
       const double D = no_arrival<KMAX>(M, Vin, base, n, load);
       const double A = arrival<JMAX>(M, Vin, m, nocc);
-      const double vn = fma(M.gamma, D, fma(M.gamma, A, r));
+      const double vn = fma(M.gamma, D, fma(M.gamma, A, fma(-M.hold, static_cast<double>(M.KC - load), r)));
       const double old = Vin[base];
       Vout[base] = vn;
       const double d = fabs(vn - old);
@@ -280,7 +282,7 @@ __device__ __forceinline__ double eval_exact(const Model& M, BufView pv, BufView
   double dmax = 0.0;
 #pragma unroll
   for (int e = 0; e < J; ++e) {
-    const double r = a[e] < M.K ? M.r_place[e] : M.r_reject[e];
+    const double r = fma(-M.hold, static_cast<double>(M.KC - load), a[e] < M.K ? M.r_place[e] : M.r_reject[e]);
     double D = M.mu_L * static_cast<double>(M.KC - load) * vs[e];
     double rs = 0.0;
 #pragma unroll

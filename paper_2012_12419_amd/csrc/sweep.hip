@@ -184,7 +184,8 @@ __global__ __launch_bounds__(kBlock) void vi_slab_kernel(Model M, int t, uint32_
           }
         }
         D = fma(M.nu_L, rs, D);
-        double best = fma(M.gamma, a_rej, M.r_reject[e]);
+        const double fu = static_cast<double>(M.KC - load);   // free units (under-utilisation penalty)
+        double best = fma(M.gamma, a_rej, fma(-M.hold, fu, M.r_reject[e]));
         const int u = M.size_idx[e];
         double ab = 0.0;
         bool an = false;
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void vi_slab_kernel(Model M, int t, uint32_
             an = any[uu];
           }
         if (an) {
-          const double q = fma(M.gamma, ab, M.r_place[e]);
+          const double q = fma(M.gamma, ab, fma(-M.hold, fu, M.r_place[e]));
           if (q > best) best = q;
         }
         const float vn = static_cast<float>(fma(M.gamma, D, best));

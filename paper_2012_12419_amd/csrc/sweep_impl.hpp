@@ -72,7 +72,8 @@ __device__ __forceinline__ double backup_occupancy(const Model& M, const float* 
         }
       }
       D = fma(M.nu_L, rs, D);
-      double best = fma(M.gamma, a_rej, M.r_reject[e]);
+      const double fu = static_cast<double>(M.KC - load);   // free units (under-utilisation penalty)
+      double best = fma(M.gamma, a_rej, fma(-M.hold, fu, M.r_reject[e]));
       const int u = M.size_idx[e];
       double ab = 0.0;
       bool an = false;
@@ -83,7 +84,7 @@ __device__ __forceinline__ double backup_occupancy(const Model& M, const float* 
           an = any[uu];
         }
       if (an) {
-        const double q = fma(M.gamma, ab, M.r_place[e]);
+        const double q = fma(M.gamma, ab, fma(-M.hold, fu, M.r_place[e]));
         if (q > best) best = q;
       }
       const float vn = static_cast<float>(fma(M.gamma, D, best));
@@ -188,8 +189,9 @@ __device__ __forceinline__ double backup_exact(const Model& M, BufView vin, floa
       rs += static_cast<double>(vr[k][e]);
     }
     D = fma(M.nu_L, rs, D);
-    double best = fma(M.gamma, a_rej, M.r_reject[e]);
-    const double q = fma(M.gamma, a_best[e], M.r_place[e]);
+    const double fu = static_cast<double>(M.KC - load);   // free units (under-utilisation penalty)
+    double best = fma(M.gamma, a_rej, fma(-M.hold, fu, M.r_reject[e]));
+    const double q = fma(M.gamma, a_best[e], fma(-M.hold, fu, M.r_place[e]));
     best = (any[e] && q > best) ? q : best;
     const float vn = static_cast<float>(fma(M.gamma, D, best));
     Vout[o + e * nocc] = vn;
@@ -262,7 +264,8 @@ __device__ __forceinline__ double backup_arrival(const Model& M, BufView vin, Bu
       rs += static_cast<double>(vr[k][e]);
     }
     D = fma(M.nu_L, rs, D);
-    const double best = fmax(fma(M.gamma, a_rej, M.r_reject[e]), fma(M.gamma, ab, M.r_place[e]));
+    const double fu = static_cast<double>(M.KC - load);   // free units (under-utilisation penalty)
+    const double best = fmax(fma(M.gamma, a_rej, fma(-M.hold, fu, M.r_reject[e])), fma(M.gamma, ab, fma(-M.hold, fu, M.r_place[e])));
     const float vn = static_cast<float>(fma(M.gamma, D, best));
     Vout[o + e * nocc] = vn;
     anew = fma(M.p[e], static_cast<double>(vn), anew);

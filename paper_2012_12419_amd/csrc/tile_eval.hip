@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void eval_tile_kernel(Model M, TileShape S,
     double anew = 0.0;
 #pragma unroll
     for (int e = 0; e < J; ++e) {
-      const double r = a[e] < K ? M.r_place[e] : M.r_reject[e];
+      const double r = fma(-M.hold, static_cast<double>(M.KC - load), a[e] < K ? M.r_place[e] : M.r_reject[e]);
       double D = idle * vs[e];
       double rs = 0.0;
 #pragma unroll

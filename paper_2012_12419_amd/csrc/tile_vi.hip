@@ -127,7 +127,8 @@ __device__ __forceinline__ void tile_backup(const Model& M, const TileHigh<K, J,
       rs += static_cast<double>(vr[k][e]);
     }
     D = fma(M.nu_L, rs, D);
-    const double best = fmax(fma(M.gamma, a_rej, M.r_reject[e]), fma(M.gamma, ab, M.r_place[e]));
+    const double fu = static_cast<double>(M.KC - load);   // free units (under-utilisation penalty)
+    const double best = fmax(fma(M.gamma, a_rej, fma(-M.hold, fu, M.r_reject[e])), fma(M.gamma, ab, fma(-M.hold, fu, M.r_place[e])));
     vn[e] = static_cast<float>(fma(M.gamma, D, best));
     anew = fma(M.p[e], static_cast<double>(vn[e]), anew);
   }

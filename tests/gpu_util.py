@@ -21,6 +21,17 @@ EVAL_REL = 1e-10
 GAP_REL = 1e-6
 
 
+def sub_solution(inst) -> float:
+    """A constant sub-solution of the Bellman operator: the lowest one-step
+    reward (paid-cloud cost on the arrival branch and the under-utilisation
+    penalty of every unit) over the discount horizon.  Value iteration from
+    it increases monotonically to an exact FP32 fixed point."""
+    lam = np.asarray(inst.lam)
+    Lam = lam.sum() + inst.K * inst.C * inst.mu + inst.K * inst.nu
+    worst = lam.sum() / Lam * max(inst.reject_cost) + inst.idle_unit_cost * inst.K * inst.C
+    return -worst / (1 - inst.gamma)
+
+
 def torch_cuda():
     import torch
     if not torch.cuda.is_available():

@@ -54,7 +54,8 @@ SMALL = [("dense_copy_K2C6", W.gradient_instance(2, 6)),
          ("small_parity", W.small_parity()),
          ("K3C5J3", W.make(3, 5, (1, 2, 3), (0.5, 0.4, 0.3), 0.12, 0.03, (1.0, 2.2, 3.1), 0.96)),
          ("reject_cost", W.make(2, 6, (1, 2), (0.7, 0.5), 0.1, 0.02, (0.3, 4.0), 0.95,
-                                reject_cost=(0.2, 0.6)))]
+                                reject_cost=(0.2, 0.6))),
+         ("penalty", W.make(3, 5, (1, 2), (0.9, 0.5), 0.1, 0.02, (1.0, 2.5), 0.95, idle_unit_cost=0.1))]
 
 
 @pytest.mark.parametrize("name,inst", SMALL, ids=[s[0] for s in SMALL])
@@ -88,7 +89,7 @@ def test_adjoint_small(mdpvi, name, inst):
     th = grad.theta_of(inst)
     J = inst.J
     assert abs(th[:J + 2] @ g[:J + 2]) <= 1e-5 * scale * np.abs(th[:J + 2]).sum()
-    if max(inst.reject_cost) == 0:
+    if max(inst.reject_cost) == 0 and inst.idle_unit_cost == 0:
         assert abs(th[J + 2:] @ g[J + 2:] - Jv) <= 1e-5 * abs(Jv)
 
 

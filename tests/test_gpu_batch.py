@@ -12,7 +12,7 @@ import pytest
 
 import workloads as W
 from oracle import vi
-from tests.gpu_util import torch_cuda, vi_close
+from tests.gpu_util import sub_solution, torch_cuda, vi_close
 
 pytestmark = pytest.mark.gpu
 
@@ -31,6 +31,7 @@ def _mixed():
     out.append(W.make(5, 6, (1, 2), (0.9, 0.4), 0.1, 0.02, (1.0, 2.4), 0.95))                 # 33,614
     out.append(W.make(1, 1, (1,), (0.5,), 0.3, 0.1, (1.0,), 0.9))                             # 2
     out.append(W.make(2, 4, (1,), (0.7,), 0.1, 0.02, (1.2,), 0.93))                           # 25
+    out.append(W.make(3, 6, (1, 2), (0.8, 0.3), 0.1, 0.02, (1.0, 2.4), 0.94, idle_unit_cost=0.15))  # 686
     return out
 
 
@@ -39,6 +40,8 @@ def test_batch_mixed_vs_oracle(mdpvi):
     insts = _mixed()
     b = mdpvi.Batch(insts)
     V = torch.zeros(b.num_states, device="cuda")
+    for i, p in enumerate(insts):
+        V[b.offsets[i]:b.offsets[i + 1]] = sub_solution(p)
     st, its, res = b.vi_solve(V, tol=1e-7)
     Vh = V.cpu().numpy()
     assert b.feasible_pairs == sum(vi.feasible_pairs(p) for p in insts)

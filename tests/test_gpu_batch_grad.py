@@ -11,7 +11,7 @@ import pytest
 
 import workloads as W
 from oracle import grad, vi
-from tests.gpu_util import EVAL_REL, gap_mask, torch_cuda
+from tests.gpu_util import sub_solution, EVAL_REL, gap_mask, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +29,7 @@ def _instances():
     out.append(W.gradient_instance(3, 6))
     out.append(W.make(4, 8, (1, 2), (1.2, 0.6), 0.1, 0.02, (1.0, 2.5), 0.97))        # 13,122 states
     out.append(W.make(2, 5, (1, 2), (0.9, 0.5), 0.1, 0.02, (0.3, 4.0), 0.95, reject_cost=(0.2, 0.5)))
+    out.append(W.make(3, 4, (1, 2), (0.8, 0.4), 0.1, 0.02, (1.0, 2.5), 0.95, idle_unit_cost=0.1))
     return out
 
 
@@ -38,10 +39,8 @@ def _batch_pipeline(mdpvi, insts):
     N = b.num_states
     V = torch.zeros(N, device="cuda")
     lb = torch.zeros(N, device="cuda")
-    for i, p in enumerate(insts):   # constant sub-solution start for instances with reject costs
-        lam = np.asarray(p.lam)
-        Lam = lam.sum() + p.K * p.C * p.mu + p.K * p.nu
-        lb[b.offsets[i]:b.offsets[i + 1]] = -lam.sum() / Lam * max(p.reject_cost) / (1 - p.gamma)
+    for i, p in enumerate(insts):   # constant sub-solution start (reject costs, penalties)
+        lb[b.offsets[i]:b.offsets[i + 1]] = sub_solution(p)
     V.copy_(lb)
     b.vi_solve(V, tol=1e-7)
     pi, _ = b.policy_extract(V, want_gap=False)

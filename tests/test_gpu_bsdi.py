@@ -14,7 +14,7 @@ import pytest
 
 import workloads as W
 from oracle import bsdi, vi
-from tests.gpu_util import VI_REL, torch_cuda, vi_close
+from tests.gpu_util import VI_REL, sub_solution, torch_cuda, vi_close
 
 pytestmark = pytest.mark.gpu
 
@@ -38,10 +38,6 @@ def bsdi_digits(p):
     return None
 
 
-def sub_solution(p):
-    lam = np.asarray(p.lam)
-    Lam = lam.sum() + p.K * p.C * p.mu + p.K * p.nu
-    return -lam.sum() / Lam * max(p.reject_cost) / (1 - p.gamma)
 
 
 CASES = [("K4C12J3", W.make(4, 12, (3, 1, 2), (0.4, 0.7, 0.2), 0.09, 0.03, (2.0, 0.7, 1.6), 0.96)),
@@ -49,7 +45,8 @@ CASES = [("K4C12J3", W.make(4, 12, (3, 1, 2), (0.4, 0.7, 0.2), 0.09, 0.03, (2.0,
          ("K6C4J2_reject", W.make(6, 4, (1, 3), (0.5, 0.3), 0.12, 0.03, (1.0, 2.9), 0.94,
                                   reject_cost=(0.1, 0.4))),
          ("K3C7J1", W.make(3, 7, (2,), (0.9,), 0.1, 0.05, (1.5,), 0.93)),
-         ("K5C6J2", W.make(5, 6, (1, 2), (0.8, 0.5), 0.1, 0.02, (1.0, 2.4), 0.95))]
+         ("K5C6J2", W.make(5, 6, (1, 2), (0.8, 0.5), 0.1, 0.02, (1.0, 2.4), 0.95)),
+         ("K4C9J2_penalty", W.make(4, 9, (1, 2), (0.6, 0.5), 0.1, 0.02, (1.0, 2.4), 0.95, idle_unit_cost=0.1))]
 
 
 @pytest.mark.parametrize("name,p", CASES, ids=[c[0] for c in CASES])

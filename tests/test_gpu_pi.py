@@ -22,7 +22,8 @@ def mdpvi():
 CASES = [("small_parity", W.small_parity()),
          ("K3C5J3", W.make(3, 5, (1, 2, 3), (0.5, 0.4, 0.3), 0.12, 0.03, (1.0, 2.2, 3.1), 0.96)),
          ("reject", W.make(2, 6, (1, 2), (0.7, 0.5), 0.1, 0.02, (0.3, 4.0), 0.95, reject_cost=(0.2, 0.6))),
-         ("tile_K4C9J3", W.make(4, 9, (1, 2, 3), (0.5, 0.4, 0.3), 0.1, 0.02, (1.0, 2.2, 3.1), 0.95))]
+         ("tile_K4C9J3", W.make(4, 9, (1, 2, 3), (0.5, 0.4, 0.3), 0.1, 0.02, (1.0, 2.2, 3.1), 0.95)),
+         ("penalty", W.make(3, 5, (1, 2), (0.6, 0.4), 0.1, 0.02, (1.0, 2.5), 0.95, idle_unit_cost=0.2))]
 
 
 @pytest.mark.parametrize("name,p", CASES, ids=[c[0] for c in CASES])

@@ -14,15 +14,13 @@ import pytest
 
 import workloads as W
 from oracle import model, vi
-from tests.gpu_util import EVAL_REL, gap_mask, torch_cuda, vi_close
+from tests.gpu_util import EVAL_REL, gap_mask, sub_solution, torch_cuda, vi_close
 
 pytestmark = pytest.mark.gpu
 
 
 def lower_bound(inst):
-    lam = np.asarray(inst.lam)
-    Lam = lam.sum() + inst.K * inst.C * inst.mu + inst.K * inst.nu
-    return -lam.sum() / Lam * max(inst.reject_cost) / (1 - inst.gamma)
+    return sub_solution(inst)
 
 
 def _cases():
@@ -36,7 +34,12 @@ def _cases():
            ("size_eq_C", W.make(3, 3, (1, 3), (0.5, 0.4), 0.15, 0.03, (1.0, 4.0), 0.95)),
            ("ragged_K4C12J3", W.make(4, 12, (1, 2, 3), (0.6, 0.5, 0.3), 0.08, 0.02, (1.0, 2.1, 3.3),
                                      0.97)),
-           ("mu0_nu0", W.make(2, 5, (1, 2), (0.6, 0.3), 0.0, 0.0, (1.0, 2.5), 0.9))]
+           ("mu0_nu0", W.make(2, 5, (1, 2), (0.6, 0.3), 0.0, 0.0, (1.0, 2.5), 0.9)),
+           # the under-utilisation penalty of Eq. (16), with and without paid-cloud costs
+           ("penalty_K3C5J2", W.make(3, 5, (1, 2), (0.6, 0.4), 0.1, 0.02, (1.0, 2.5), 0.95,
+                                     idle_unit_cost=0.2)),
+           ("penalty_reject", W.make(2, 6, (1, 3), (0.9, 0.3), 0.12, 0.03, (0.4, 3.5), 0.93,
+                                     reject_cost=(0.3, 0.1), idle_unit_cost=0.05))]
     for seed in range(6):
         out.append((f"random{seed}", W.random_small(seed, K_max=4, C_max=6)))
     for seed in range(3):
@@ -239,7 +242,10 @@ FORM_CASES = [("small_parity", W.small_parity()),
               # K = 3: T = 2, 64 occupancies per tile (idle threads)
               ("tile_K3C7J1", W.make(3, 7, (2,), (0.9,), 0.1, 0.05, (1.5,), 0.93)),
               # the automatic choice takes the tile form: 256 tiles of 256 occupancies
-              ("tile_auto_K8C3J2", W.make(8, 3, (1, 2), (0.7, 0.4), 0.15, 0.03, (1.0, 2.2), 0.92))]
+              ("tile_auto_K8C3J2", W.make(8, 3, (1, 2), (0.7, 0.4), 0.15, 0.03, (1.0, 2.2), 0.92)),
+              # the under-utilisation penalty on the tile form
+              ("tile_penalty_K4C9J3", W.make(4, 9, (1, 2, 3), (0.5, 0.4, 0.3), 0.1, 0.02, (1.0, 2.2, 3.1),
+                                             0.95, reject_cost=(0.2, 0.0, 0.1), idle_unit_cost=0.08))]
 
 def _forms(mdpvi, inst):
     forms = [0]
@@ -269,7 +275,7 @@ def test_sweep_forms_bit_identical(mdpvi, name, inst):
     ref = None
     for f in forms + [-1]:
         mdp.set_sweep_form(f)
-        V = torch.zeros(mdp.num_states, device="cuda")
+        V = torch.full((mdp.num_states,), sub_solution(inst), device="cuda")
         st = mdp.vi_solve(V, tol=1e-7)
         got = (V.cpu().numpy().view(np.uint32).copy(), st["iterations"])
         print(f"{name}: form {f}: {st['iterations']} sweeps", flush=True)

@@ -39,6 +39,7 @@ class Instance:
     reward: tuple
     reject_cost: tuple
     gamma: float
+    idle_unit_cost: float = 0.0
 
     def as_dict(self) -> dict:
         return asdict(self)
@@ -57,7 +58,7 @@ class Instance:
 
 def make(K: int, C: int, size: Sequence[int], lam: Sequence[float], mu: float,
          nu: float, reward: Sequence[float], gamma: float,
-         reject_cost: Optional[Sequence[float]] = None) -> Instance:
+         reject_cost: Optional[Sequence[float]] = None, idle_unit_cost: float = 0.0) -> Instance:
     J = len(size)
     if reject_cost is None:
         reject_cost = [0.0] * J
@@ -65,7 +66,7 @@ def make(K: int, C: int, size: Sequence[int], lam: Sequence[float], mu: float,
                     lam=tuple(float(x) for x in lam), mu=float(mu), nu=float(nu),
                     reward=tuple(float(x) for x in reward),
                     reject_cost=tuple(float(x) for x in reject_cost),
-                    gamma=float(gamma))
+                    gamma=float(gamma), idle_unit_cost=float(idle_unit_cost))
 
 
 def _draw_rates(rng: np.random.Generator, K: int, C: int, J: int, gamma: Optional[float]):
