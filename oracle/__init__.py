@@ -16,6 +16,11 @@ exact   exact rational (``fractions.Fraction``) solves and brute force over
 grad    gradient of the expected discounted reward from the empty system
         with respect to (lambda_j, mu, nu, r_j): dense autograd, sparse
         adjoint and central finite differences.
+bsdi    block-asynchronous value iteration on occupancy tiles (Alg. 4).
+pi      policy iteration with a near-tie guard (Alg. 3 step 4 repeated).
+static_bot  the fast greedy heuristic (Alg. 2) on a static set of bags of
+        tasks, the cloud-wide reward of a placement (Eqs. (14)-(16)) and the
+        best placement by search (Sec. VII example).
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_*.py`` against closed forms, textbook identities, brute
