@@ -119,6 +119,33 @@ def policy_iteration_run(mdp, eval_tol: float) -> dict:
             "seconds": time.perf_counter() - t0, "eval_tol": eval_tol, "improve_tol": 1e-7}
 
 
+def static_bot_run(mdpvi, n: int) -> dict:
+    """Fast greedy placement (Alg. 2) of the static example (11 VCs, 11 bags,
+    55 tasks) and of n random scenarios of the same shape, timed."""
+    import numpy as np
+    import torch
+    from workloads import static_bot as ws
+    caps, need, _ = ws.example()
+    consts = (ws.EXAMPLE_BETA_VC, ws.EXAMPLE_BETA_TC, ws.EXAMPLE_GAMMA_VC)
+    ex = mdpvi.static_first_fit(torch.from_numpy(caps[None]).cuda(), torch.from_numpy(need[None]).cuda(),
+                                *consts)
+    tot = ex["totals"][0].tolist()
+    c, d = ws.random_scenarios(n, len(caps), need.size, seed=99, cap_max=45, need_max=11)
+    c, d = torch.from_numpy(c).cuda(), torch.from_numpy(d).cuda()
+    mdpvi.static_first_fit(c, d, *consts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        mdpvi.static_first_fit(c, d, *consts)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    return {"example": {"vc_vms": tot[0], "paid_vms": tot[1], "idle_vms": tot[2],
+                        "greedy_reward": float(ex["reward"][0])},
+            "scenarios": n, "tasks_per_scenario": int(need.size), "seconds": sec,
+            "scenarios_per_s": n / sec}
+
+
 def _sub_solution(p):
     """A constant sub-solution of the Bellman operator: the least one-step
     reward over the discount horizon (value iteration from it is monotone)."""
@@ -267,6 +294,8 @@ def main() -> int:
                     help="skip the block-asynchronous (BSDI) comparison")
     ap.add_argument("--grad-batch", type=int, default=256,
                     help="instances of the batched gradient pipeline (0: skip the gradient fields)")
+    ap.add_argument("--static", type=int, default=1_000_000,
+                    help="random static scenarios for the first-fit placement timing (0: skip)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -430,6 +459,8 @@ def main() -> int:
         out["batched_vs_per_instance"] = batched_vs_per_instance(mdpvi, args.batch, args.tol)
     if args.grad_batch:
         out["gradient"] = gradient_workloads(mdpvi, args.grad_batch, args.tol)
+    if args.static:
+        out["static_bot"] = static_bot_run(mdpvi, args.static)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps)
     print(json.dumps(out), flush=True)

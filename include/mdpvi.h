@@ -335,6 +335,45 @@ int mdp_autotune(mdpvi_mdp_t h, const float *V, int32_t trials, void *hip_stream
  * event records per sweep).  Errors: MDPVI_EINVAL (NULL handle).           */
 int mdp_set_timing(mdpvi_mdp_t h, int32_t per_sweep_events);
 
+/* ---- Static bags of tasks (Alg. 2; the example of Sec. VII) ------------
+ * B independent scenarios, each K vehicular clouds (VCs) with free VM
+ * capacities and T task slots in arrival order (bag by bag, tasks of a bag
+ * in order).  Layouts, all device arrays, row-major by scenario:
+ *   caps   int32 [B][K]   free VMs of each VC, in [0, 2^30]
+ *   need   int32 [B][T]   VMs a task needs, in [0, 2^30]; 0 = empty slot
+ *   place  int32 [B][T]   VC index, MDPVI_STATIC_PAID, or MDPVI_STATIC_EMPTY
+ *   used   int32 [B][K]   VMs taken on each VC
+ *   totals int64 [B][3]   (VMs in VCs, VMs in the paid cloud, idle VMs left in VCs)
+ *   reward double [B]     beta_vc*vc - beta_tc*paid - gamma_vc*idle (Eqs. (14)-(16)
+ *                         summed over the cloud; each product rounded, then
+ *                         subtracted left to right)
+ *   status int32 [B]      0 ok; 1 a capacity, 2 a need out of range; 3 a VC
+ *                         over capacity, 4 a place code outside [-1, K) on a
+ *                         task (static_score only).  A scenario with a nonzero
+ *                         status gets no other output.
+ * need and place may be NULL when T = 0; B = 0 is a no-op.  K in [1, 64],
+ * beta_vc, beta_tc, gamma_vc finite.  Both calls are asynchronous on the
+ * stream.  Errors (host-side argument checks only): MDPVI_EINVAL,
+ * MDPVI_ERANGE (B above 2^33 - 4 or B*T above 2^62), MDPVI_EDEVICE.        */
+#define MDPVI_STATIC_MAX_K 64
+#define MDPVI_STATIC_PAID (-1)
+#define MDPVI_STATIC_EMPTY (-2)
+
+/* The fast greedy heuristic of Alg. 2: each task goes to the first VC, in
+ * index order, that still has need[t] free VMs, and takes them; if no VC
+ * has, it goes to the paid cloud.  Writes place, used, totals, reward and
+ * status.                                                                   */
+int static_first_fit(const int32_t *caps, const int32_t *need, int64_t B, int32_t K, int64_t T,
+                     double beta_vc, double beta_tc, double gamma_vc, int32_t *place, int32_t *used,
+                     int64_t *totals, double *reward, int32_t *status, void *hip_stream);
+
+/* Score a given placement (for instance the best one, or an MDP's): place is
+ * read, not written (codes on empty slots are ignored).  Writes used, totals,
+ * reward and status.                                                        */
+int static_score(const int32_t *caps, const int32_t *need, const int32_t *place, int64_t B, int32_t K,
+                 int64_t T, double beta_vc, double beta_tc, double gamma_vc, int32_t *used,
+                 int64_t *totals, double *reward, int32_t *status, void *hip_stream);
+
 /* Thread-local text of the last failure ("" if none). */
 const char *mdpvi_last_error(void);
 

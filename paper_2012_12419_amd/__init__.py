@@ -31,6 +31,8 @@ ENAN = -4
 EDEVICE = -5
 ENOMEM = -6
 FORM_TILE = 16   # mdp_set_sweep_form: the tile form
+STATIC_PAID = -1    # static placement: the task went to the paid cloud
+STATIC_EMPTY = -2   # static placement: empty task slot (need 0)
 _NAMES = {EINVAL: "EINVAL", ERANGE: "ERANGE", ENOCONV: "ENOCONV", ENAN: "ENAN",
           EDEVICE: "EDEVICE", ENOMEM: "ENOMEM"}
 
@@ -97,6 +99,10 @@ SIGNATURES = {
     "mdp_sweep_forms": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32)]),
     "mdp_autotune": (ctypes.c_int, [_vp, _vp, _c_int32, _vp, ctypes.POINTER(_c_int32),
                                     ctypes.POINTER(_c_double)]),
+    "static_first_fit": (ctypes.c_int, [_vp, _vp, _c_int64, _c_int32, _c_int64, _c_double, _c_double,
+                                        _c_double, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "static_score": (ctypes.c_int, [_vp, _vp, _vp, _c_int64, _c_int32, _c_int64, _c_double, _c_double,
+                                    _c_double, _vp, _vp, _vp, _vp, _vp]),
     "mdpvi_last_error": (ctypes.c_char_p, []),
 }
 
@@ -434,3 +440,52 @@ class Batch:
             out.append(list(g[at:at + 2 * J + 2]))
             at += 2 * J + 2
         return out, list(obj), w, st.as_dict(), list(its)
+
+
+def _static_args(caps, need):
+    import torch
+    if caps.dim() != 2 or need.dim() != 2 or caps.shape[0] != need.shape[0]:
+        raise ValueError("caps must be [B, K] and need [B, T] with the same B")
+    B, K = caps.shape
+    T = need.shape[1]
+    c = _dev_tensor(caps, torch.int32, B * K, "caps")
+    n = _dev_tensor(need, torch.int32, B * T, "need")
+    out = dict(used=torch.empty((B, K), dtype=torch.int32, device=caps.device),
+               totals=torch.empty((B, 3), dtype=torch.int64, device=caps.device),
+               reward=torch.empty(B, dtype=torch.float64, device=caps.device),
+               status=torch.empty(B, dtype=torch.int32, device=caps.device))
+    return B, K, T, c, n, out
+
+
+def static_first_fit(caps, need, beta_vc: float = 1.0, beta_tc: float = 1.2, gamma_vc: float = 1.0,
+                     stream=None):
+    """Fast greedy placement (Alg. 2) of B static scenarios: caps int32 [B, K]
+    free VMs per VC, need int32 [B, T] VMs per task in arrival order (0 =
+    empty slot).  Returns dict(place [B, T], used [B, K], totals [B, 3] =
+    (VC VMs, paid VMs, idle VMs), reward [B], status [B]); asynchronous."""
+    import torch
+    B, K, T, c, n, out = _static_args(caps, need)
+    out["place"] = torch.empty((B, T), dtype=torch.int32, device=caps.device)
+    _check(load().static_first_fit(c, n, B, K, T, beta_vc, beta_tc, gamma_vc,
+                                   ctypes.c_void_p(out["place"].data_ptr()),
+                                   ctypes.c_void_p(out["used"].data_ptr()),
+                                   ctypes.c_void_p(out["totals"].data_ptr()),
+                                   ctypes.c_void_p(out["reward"].data_ptr()),
+                                   ctypes.c_void_p(out["status"].data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def static_score(caps, need, place, beta_vc: float = 1.0, beta_tc: float = 1.2, gamma_vc: float = 1.0,
+                 stream=None):
+    """Cloud-wide reward (Eqs. (14)-(16)) of a given placement place int32
+    [B, T] (VC index or STATIC_PAID).  Returns dict(used, totals, reward,
+    status); asynchronous."""
+    import torch
+    B, K, T, c, n, out = _static_args(caps, need)
+    p = _dev_tensor(place, torch.int32, B * T, "place")
+    _check(load().static_score(c, n, p, B, K, T, beta_vc, beta_tc, gamma_vc,
+                               ctypes.c_void_p(out["used"].data_ptr()),
+                               ctypes.c_void_p(out["totals"].data_ptr()),
+                               ctypes.c_void_p(out["reward"].data_ptr()),
+                               ctypes.c_void_p(out["status"].data_ptr()), _stream_ptr(stream)))
+    return out

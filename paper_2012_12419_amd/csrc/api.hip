@@ -1382,3 +1382,52 @@ int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t* pi, const double* V_pi, flo
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- static bags of tasks
+
+namespace {
+
+int check_static(const int32_t* caps, const int32_t* need, const void* place, int64_t B, int32_t K, int64_t T,
+                 double bvc, double btc, double gvc, const void* used, const void* totals,
+                 const void* reward, const void* status) {
+  if (B < 0 || T < 0) return fail(MDPVI_EINVAL, "B=%lld and T=%lld must be >= 0", (long long)B, (long long)T);
+  if (K < 1 || K > MDPVI_STATIC_MAX_K) return fail(MDPVI_EINVAL, "K=%d must be in [1, %d]", K, MDPVI_STATIC_MAX_K);
+  if (B > 4LL * 0x7fffffffLL) return fail(MDPVI_ERANGE, "B=%lld scenarios exceed the grid", (long long)B);
+  if (T > 0 && B > (int64_t(1) << 62) / T) return fail(MDPVI_ERANGE, "B*T overflows");
+  if (!is_finite(bvc) || !is_finite(btc) || !is_finite(gvc))
+    return fail(MDPVI_EINVAL, "beta_vc, beta_tc and gamma_vc must be finite");
+  if (B == 0) return MDPVI_OK;
+  if (!caps || !used || !totals || !reward || !status) return fail(MDPVI_EINVAL, "NULL array");
+  if (T > 0 && (!need || !place)) return fail(MDPVI_EINVAL, "NULL task array with T > 0");
+  return MDPVI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int static_first_fit(const int32_t* caps, const int32_t* need, int64_t B, int32_t K, int64_t T,
+                     double beta_vc, double beta_tc, double gamma_vc, int32_t* place, int32_t* used,
+                     int64_t* totals, double* reward, int32_t* status, void* hip_stream) {
+  const int rc = check_static(caps, need, place, B, K, T, beta_vc, beta_tc, gamma_vc, used, totals, reward,
+                              status);
+  if (rc != MDPVI_OK) return rc;
+  HIP_TRY(mdpvi::launch_static_first_fit(B, K, T, caps, need, beta_vc, beta_tc, gamma_vc, place, used,
+                                         reinterpret_cast<long long*>(totals), reward, status,
+                                         static_cast<hipStream_t>(hip_stream)));
+  return MDPVI_OK;
+}
+
+int static_score(const int32_t* caps, const int32_t* need, const int32_t* place, int64_t B, int32_t K,
+                 int64_t T, double beta_vc, double beta_tc, double gamma_vc, int32_t* used, int64_t* totals,
+                 double* reward, int32_t* status, void* hip_stream) {
+  const int rc = check_static(caps, need, place, B, K, T, beta_vc, beta_tc, gamma_vc, used, totals, reward,
+                              status);
+  if (rc != MDPVI_OK) return rc;
+  HIP_TRY(mdpvi::launch_static_score(B, K, T, caps, need, place, beta_vc, beta_tc, gamma_vc, used,
+                                     reinterpret_cast<long long*>(totals), reward, status,
+                                     static_cast<hipStream_t>(hip_stream)));
+  return MDPVI_OK;
+}
+
+}  // extern "C"

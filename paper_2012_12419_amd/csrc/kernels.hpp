@@ -133,4 +133,13 @@ hipError_t launch_batch_grad(const BatchInst* insts, const Tile* tiles, int n_ti
                              int n, int maxK, int maxJ, const uint8_t* pi, const double* V, const float* w,
                              double* partial, double* out, hipStream_t s);
 
+// Static bag-of-task placement (static_bot.hip): B scenarios of K <= 64 VCs
+// and T task slots, one wavefront per scenario.
+hipError_t launch_static_first_fit(long long B, int K, long long T, const int32_t* caps, const int32_t* need,
+                                   double bvc, double btc, double gvc, int32_t* place, int32_t* used,
+                                   long long* totals, double* reward, int32_t* status, hipStream_t s);
+hipError_t launch_static_score(long long B, int K, long long T, const int32_t* caps, const int32_t* need,
+                               const int32_t* place, double bvc, double btc, double gvc, int32_t* used,
+                               long long* totals, double* reward, int32_t* status, hipStream_t s);
+
 }  // namespace mdpvi
