@@ -52,6 +52,8 @@ struct mdpvi_mdp {
   int slab_t = -1;              // sweep form: -1 automatic, 0 direct, t > 0 slab of t digits,
                                 // MDPVI_FORM_TILE the tile form
   hipEvent_t* sweep_ev = nullptr;   // 2 * kMaxChunk events (created on demand)
+  uint32_t* tile_order[3][2] = {};   // device tile orders of T = 2, 3, 4: bisection, dealt runs
+  uint32_t tile_order_run[3] = {};   // run length of the dealt orders
 };
 
 namespace {
@@ -233,6 +235,63 @@ int eval_form(mdpvi_mdp* h, mdpvi::TileShape* S) {
 
 int eval_run(mdpvi_mdp* h, const uint8_t* pi, double* V, double tol, int64_t max_iter, hipStream_t s,
              mdpvi_stats* st);
+
+// Tile orders: for a sweep whose working set (values and arrival terms read
+// and written) fits the last-level cache, recursive coordinate bisection
+// (each XCD a compact block: fewest halo lines through its L2); beyond it,
+// runs of kDealRun tiles dealt round-robin (all XCDs on one region, whose
+// neighbour planes then stay in the last-level cache).
+constexpr double kLlcBytes = 256.0 * 1024 * 1024;
+constexpr uint32_t kDealRun = 16;
+
+// Points S->order at the handle's device copy of the tile order for S's tile
+// depth and a sweep working set of ws bytes, built and uploaded on first
+// use.  The environment variable MDPVI_TILE_ORDER (a measurement aid)
+// overrides the choice: "index" (contiguous eighths of the index order),
+// "rcb", or "dealN" (runs of N tiles dealt round-robin).
+int set_tile_order(mdpvi_mdp* h, mdpvi::TileShape* S, double ws) {
+  static const std::string forced = [] {
+    const char* e = std::getenv("MDPVI_TILE_ORDER");
+    return std::string(e ? e : "");
+  }();
+  S->order = nullptr;
+  if (forced == "index") return MDPVI_OK;
+  if (S->T < 2 || S->T > 4) return fail(MDPVI_EINVAL, "tile depth %d outside [2, 4]", S->T);
+  uint32_t run = ws <= kLlcBytes ? 0u : kDealRun;   // 0: bisection
+  if (forced == "rcb") run = 0;
+  if (forced.rfind("deal", 0) == 0) run = static_cast<uint32_t>(std::max(1, std::atoi(forced.c_str() + 4)));
+  uint32_t*& d = h->tile_order[S->T - 2][run ? 1 : 0];
+  uint32_t& d_run = h->tile_order_run[S->T - 2];
+  if (d && run && d_run != run) {   // another dealt run length was forced
+    (void)hipFree(d);
+    d = nullptr;
+  }
+  if (!d) {
+    std::vector<uint32_t> order;
+    if (run)
+      mdpvi::tile_deal(*S, run, &order);
+    else
+      mdpvi::tile_partition(h->M.K, h->M.R, *S, &order);
+    if (hipMalloc(reinterpret_cast<void**>(&d), order.size() * sizeof(uint32_t)) != hipSuccess) {
+      d = nullptr;
+      return fail(MDPVI_ENOMEM, "hipMalloc of the tile order failed");
+    }
+    const hipError_t e = hipMemcpy(d, order.data(), order.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      d = nullptr;
+      return fail_hip(e, "hipMemcpy(tile order)");
+    }
+    if (run) d_run = run;
+  }
+  S->order = d;
+  return MDPVI_OK;
+}
+
+// Bytes a sweep reads and writes once: values in and out, arrival terms in
+// and out, and for evaluation the policy.
+double vi_working_set(const Model& M) { return 8.0 * M.n_states + 16.0 * M.n_occ; }
+double eval_working_set(const Model& M) { return 17.0 * M.n_states + 16.0 * M.n_occ; }
 
 double bits_to_double(unsigned long long b) {
   double d;
@@ -568,6 +627,9 @@ void mdp_free(mdpvi_mdp_t h) {
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   if (h->aux) (void)hipFree(h->aux);
+  for (auto& per_t : h->tile_order)
+    for (uint32_t* o : per_t)
+      if (o) (void)hipFree(o);
   if (h->out_host) (void)hipHostFree(h->out_host);
   if (h->sweep_ev) {
     for (int64_t i = 0; i < 2 * kMaxChunk; ++i)
@@ -631,8 +693,11 @@ int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream
     }
   }
   mdpvi::TileShape S{};
-  if (mdpvi::vi_tile_shape(M, &S))
+  if (mdpvi::vi_tile_shape(M, &S)) {
     for (int w = 0; w <= 4; ++w) forms.push_back(MDPVI_FORM_TILE + w);
+    rc = set_tile_order(h, &S, vi_working_set(M));
+    if (rc) return rc;
+  }
   float* out = static_cast<float*>(h->vbuf);
   double* A[2] = {nullptr, nullptr};
   if (mdpvi::exact_shape(M) || is_tile_form(forms.back())) {
@@ -700,6 +765,10 @@ int vi_solve(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, void* hip_st
     int arc = arrival_arrays(h, V, s, A);
     if (arc) return arc;
   }
+  if (is_tile_form(form)) {
+    int orc = set_tile_order(h, &S, vi_working_set(M));
+    if (orc) return orc;
+  }
   if (is_tile_form(form))
     return run_loop<float>(h, V, tol, max_iter, s, st, 8.0 * M.n_states,
                            static_cast<double>(h->feasible_pairs),
@@ -733,6 +802,8 @@ int vi_solve_bsdi(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, int32_t
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   double* A[2] = {nullptr, nullptr};
   rc = arrival_arrays(h, V, s, A);
+  if (rc) return rc;
+  rc = set_tile_order(h, &S, vi_working_set(M));
   if (rc) return rc;
   return run_loop<float>(h, V, tol, max_iter, s, st, 8.0 * M.n_states,
                          static_cast<double>(h->feasible_pairs) * inner,
@@ -792,6 +863,8 @@ int eval_run(mdpvi_mdp* h, const uint8_t* pi, double* V, double tol, int64_t max
       return fail(MDPVI_ENOMEM, "hipMalloc of the arrival-term arrays failed");
     }
     double* A[2] = {h->abuf, h->abuf + per};
+    int orc = set_tile_order(h, &S, eval_working_set(M));
+    if (orc) return orc;
     HIP_TRY(mdpvi::launch_eval_arrival_init(M, V, A[0], s));
     return run_loop<double>(h, V, tol, max_iter, s, st, 17.0 * M.n_states,
                             static_cast<double>(M.n_states),

@@ -109,8 +109,9 @@ enum class ResKind { kMax, kSum };
 // End of a max-norm sweep: the workgroup's largest |V' - V| is stored to
 // res[r * grid + b]; if it is not below tol the workgroup raises go[r]
 // (and nan[r] for a NaN).  No atomics.
+template <int NB = kBlock>
 __device__ __forceinline__ void block_max_to(double v, Ctl* ctl, double* res, long long j, double tol) {
-  __shared__ double part[kBlock / kWave];
+  __shared__ double part[NB / kWave];
   v = wave_max(v);
   const int lane = threadIdx.x % kWave;
   const int wid = threadIdx.x / kWave;
@@ -119,7 +120,7 @@ __device__ __forceinline__ void block_max_to(double v, Ctl* ctl, double* res, lo
   if (threadIdx.x == 0) {
     double m = part[0];
 #pragma unroll
-    for (int w = 1; w < kBlock / kWave; ++w) m = (part[w] > m || part[w] != part[w]) ? part[w] : m;
+    for (int w = 1; w < NB / kWave; ++w) m = (part[w] > m || part[w] != part[w]) ? part[w] : m;
     const int r = static_cast<int>(j % kResSlots);
     const int x = blockIdx.x % kNumXcd;
     res[static_cast<size_t>(r) * gridDim.x + blockIdx.x] = m;

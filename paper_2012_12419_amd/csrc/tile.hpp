@@ -2,10 +2,11 @@
 // fixed-policy evaluation).
 //
 // A tile is the set of (C+1)^T occupancies that share the high digits
-// n_T..n_{K-1}; one workgroup per tile, tiles in index order (XCD-aware), so
-// the traversal of the occupancy grid is the linear one of the direct form
-// and neighbouring tiles share an XCD's L2.  The workgroup stages its tile's
-// values (all classes) and FP64 arrival terms in LDS; then every neighbour
+// n_T..n_{K-1}; one workgroup per tile, in a host-computed order that gives
+// each XCD a compact block of tiles (or, for sweeps beyond the last-level
+// cache, keeps all XCDs on one region).  The workgroup stages its tile's
+// values (all classes; value iteration also its FP64 arrival terms) in LDS;
+// then every neighbour
 // along a low digit (release, reset, placement) is an LDS read, and every
 // neighbour along a high digit is a global load at the thread's own offset
 // plus a workgroup-uniform offset (a scalar register of the buffer load),
@@ -19,7 +20,10 @@
 
 #include "device.hpp"
 
+#include <algorithm>
+#include <functional>
 #include <type_traits>
+#include <vector>
 
 namespace mdpvi {
 
@@ -27,6 +31,16 @@ namespace mdpvi {
 // arrival array: a placement without room along a high digit reads entry
 // n_occ + i (i < tile size <= kSentinel).
 constexpr uint32_t kSentinel = 4096;
+// Threads of a tile workgroup and the waves per SIMD the register budget of
+// the tile kernels must allow (the compiler caps VGPRs at 512 / that).
+#ifndef MDPVI_TILE_BLOCK
+#define MDPVI_TILE_BLOCK 256
+#endif
+#ifndef MDPVI_TILE_MIN_WAVES
+#define MDPVI_TILE_MIN_WAVES 1
+#endif
+constexpr int kTileBlock = MDPVI_TILE_BLOCK;
+constexpr int kTileMinWaves = MDPVI_TILE_MIN_WAVES;
 // LDS bytes a tile image may take (the block-asynchronous form holds two).
 constexpr uint32_t kTileLds = 48 * 1024;
 constexpr uint32_t kBsdiLds = 64 * 1024;
@@ -37,26 +51,103 @@ struct TileShape {
   int32_t T;       // low digits of a tile
   uint32_t grid;   // workgroups launched: n (one tile each), or a multiple of 8
                    // that walk the tiles of their XCD's range in order
+  const uint32_t* order;   // device [n]: the tiles of XCD 0, then of XCD 1, ...
+                           // (tile_partition); nullptr: index order
 };
 
-// Tiles of workgroup blockIdx.x: with one workgroup per tile, the XCD-aware
-// order of the direct form; otherwise XCD x (workgroups b with b % 8 = x)
-// owns tiles [x n / 8, (x+1) n / 8), which its grid / 8 workgroups take in
-// index order, so that the tiles in flight on an XCD form a sliding window.
+// Positions of workgroup blockIdx.x in the tile order.  Workgroups are
+// handed to the 8 XCDs round-robin by their id, so XCD x runs the
+// workgroups b = x (mod 8): with one workgroup per tile it runs
+// count_x = ceil((n - x) / 8) of them, and owns positions [start_x,
+// start_x + count_x) of the order; its walkers (grid < n) take those
+// positions in turn, so that the tiles in flight on an XCD stay close.
+// Without an order table the positions are tile indices (contiguous ranges
+// per XCD, as in the direct form).
 struct TileWalk {
   uint32_t first, end, step;
 };
 
+__host__ __device__ inline uint32_t tile_xcd_count(uint32_t n, uint32_t x) {
+  return (n + kNumXcd - 1 - x) / kNumXcd;
+}
+
+__host__ __device__ inline uint32_t tile_xcd_start(uint32_t n, uint32_t x) {
+  const uint32_t rem = n % kNumXcd;
+  return x * (n / kNumXcd) + (x < rem ? x : rem);
+}
+
 __device__ __forceinline__ TileWalk tile_walk(const TileShape& S) {
+  const uint32_t x = blockIdx.x % kNumXcd;
+  const uint32_t w = blockIdx.x / kNumXcd;
+  if (S.order) {
+    const uint32_t lo = tile_xcd_start(S.n, x);
+    if (S.grid == S.n) return TileWalk{lo + w, lo + w + 1, 1};
+    return TileWalk{lo + w, lo + tile_xcd_count(S.n, x), gridDim.x / kNumXcd};
+  }
   if (S.grid == S.n) {
     const uint32_t t = xcd_block(blockIdx.x, gridDim.x);
     return TileWalk{t, t + 1, 1};
   }
-  const uint32_t x = blockIdx.x % kNumXcd;
-  const uint32_t w = blockIdx.x / kNumXcd;
   const uint32_t lo = static_cast<uint32_t>(static_cast<uint64_t>(S.n) * x / kNumXcd);
   const uint32_t hi = static_cast<uint32_t>(static_cast<uint64_t>(S.n) * (x + 1) / kNumXcd);
   return TileWalk{lo + w, hi, gridDim.x / kNumXcd};
+}
+
+// The tile at walk position p (a workgroup-uniform scalar load).
+__device__ __forceinline__ uint32_t tile_at(const TileShape& S, uint32_t p) {
+  return S.order ? S.order[p] : p;
+}
+
+// Host: the tile order of a shape.  The n tiles are points of the
+// (C+1)^(K-T) grid of high digits; recursive coordinate bisection splits
+// them into 8 parts of count_x tiles, each split cutting the current set
+// across its widest digit (the higher digit on ties) at the rank that gives
+// each side its count, ties on that digit broken by tile index.  Every XCD
+// then owns a compact block of tiles instead of a slab one or two values
+// thick along the top digit: the neighbours it fetches from other XCDs'
+// tiles (the halo of release, reset and placement reads along the high
+// digits) shrink with the block's surface.  Within a part, tiles keep index
+// order.
+inline void tile_partition(int K, int R, const TileShape& S, std::vector<uint32_t>* order) {
+  const int H = K - S.T;
+  const uint32_t n = S.n;
+  std::vector<uint32_t> ids(n);
+  for (uint32_t i = 0; i < n; ++i) ids[i] = i;
+  std::vector<uint32_t> pw(H);
+  for (int h = 0; h < H; ++h) pw[h] = h == 0 ? 1u : pw[h - 1] * static_cast<uint32_t>(R);
+  auto digit = [&](uint32_t t, int h) { return static_cast<int>((t / pw[h]) % static_cast<uint32_t>(R)); };
+  order->assign(n, 0u);
+  // split ids[lo, hi) among XCDs [x0, x1)
+  std::function<void(uint32_t, uint32_t, int, int)> split = [&](uint32_t lo, uint32_t hi, int x0, int x1) {
+    if (x1 - x0 == 1) {
+      std::sort(ids.begin() + lo, ids.begin() + hi);
+      std::copy(ids.begin() + lo, ids.begin() + hi, order->begin() + tile_xcd_start(n, x0));
+      return;
+    }
+    const int xm = (x0 + x1) / 2;
+    uint32_t left = 0;
+    for (int x = x0; x < xm; ++x) left += tile_xcd_count(n, static_cast<uint32_t>(x));
+    int axis = H - 1, widest = -1;
+    for (int h = H - 1; h >= 0; --h) {
+      int mn = R, mx = -1;
+      for (uint32_t i = lo; i < hi; ++i) {
+        const int d = digit(ids[i], h);
+        mn = d < mn ? d : mn;
+        mx = d > mx ? d : mx;
+      }
+      if (mx - mn > widest) {
+        widest = mx - mn;
+        axis = h;
+      }
+    }
+    std::sort(ids.begin() + lo, ids.begin() + hi, [&](uint32_t a, uint32_t b) {
+      const int da = digit(a, axis), db = digit(b, axis);
+      return da != db ? da < db : a < b;
+    });
+    split(lo, lo + left, x0, xm);
+    split(lo + left, hi, xm, x1);
+  };
+  split(0, n, 0, kNumXcd);
 }
 
 // The deepest tile (T in 2..min(4, K-1)) whose LDS footprint of
@@ -97,6 +188,86 @@ inline void tile_set_walkers(TileShape* S, int w, int cus) {
   if (g < kNumXcd) g = kNumXcd;
   if (g >= S->n) g = S->n;   // one tile each (the direct order)
   S->grid = g;
+}
+
+// Stages a tile's values (J classes of TV, class c at byte offset
+// o0 * sizeof(TV) + c * cls) and arrival terms into Vl [J][occ] and Al [occ]
+// with NB threads.  Loads are issued in batches of kStageRounds rounds per
+// thread before the first LDS write, so that a thread waits for one round
+// trip per batch instead of one per round; lanes past the tile load the last
+// occupancy again (in bounds) and write nothing.
+constexpr int kStageRounds = 8;
+
+template <int J, int NB, typename TV>
+__device__ __forceinline__ void stage_tile(uint32_t occ, uint32_t o0, uint32_t cls, BufView vin, BufView ain,
+                                           TV* Vl, double* Al) {
+  constexpr uint32_t tv = sizeof(TV);
+  for (uint32_t base = 0; base < occ; base += kStageRounds * NB) {
+    TV v[kStageRounds][J];
+    double a[kStageRounds];
+#pragma unroll
+    for (int r = 0; r < kStageRounds; ++r) {
+      uint32_t i = base + r * NB + threadIdx.x;
+      i = i < occ ? i : occ - 1;
+#pragma unroll
+      for (int e = 0; e < J; ++e) {
+        if constexpr (tv == 4)
+          v[r][e] = ld_f32(vin, i * 4u, o0 * 4u + e * cls);
+        else
+          v[r][e] = ld_f64(vin, i * 8u, o0 * 8u + e * cls);
+      }
+      a[r] = ld_f64(ain, i * 8u, o0 * 8u);
+    }
+#pragma unroll
+    for (int r = 0; r < kStageRounds; ++r) {
+      const uint32_t i = base + r * NB + threadIdx.x;
+      if (i < occ) {
+#pragma unroll
+        for (int e = 0; e < J; ++e) Vl[e * occ + i] = v[r][e];
+        Al[i] = a[r];
+      }
+    }
+  }
+}
+
+// Stages only the tile's values (FP64, J classes) into Vl [J][occ], in the
+// batches of stage_tile.
+template <int J, int NB>
+__device__ __forceinline__ void stage_values(uint32_t occ, uint32_t o0, uint32_t cls, BufView vin, double* Vl) {
+  for (uint32_t base = 0; base < occ; base += kStageRounds * NB) {
+    double v[kStageRounds][J];
+#pragma unroll
+    for (int r = 0; r < kStageRounds; ++r) {
+      uint32_t i = base + r * NB + threadIdx.x;
+      i = i < occ ? i : occ - 1;
+#pragma unroll
+      for (int e = 0; e < J; ++e) v[r][e] = ld_f64(vin, i * 8u, o0 * 8u + e * cls);
+    }
+#pragma unroll
+    for (int r = 0; r < kStageRounds; ++r) {
+      const uint32_t i = base + r * NB + threadIdx.x;
+      if (i < occ) {
+#pragma unroll
+        for (int e = 0; e < J; ++e) Vl[e * occ + i] = v[r][e];
+      }
+    }
+  }
+}
+
+// Host: runs of `run` consecutive tiles dealt to the XCDs in turn (an XCD
+// whose share is full passes its run to the next), so that all XCDs sweep
+// the same region of the grid at the same time: for sweeps whose working set
+// exceeds the last-level cache, the neighbour planes of that region are then
+// read from it by every XCD instead of from HBM.
+inline void tile_deal(const TileShape& S, uint32_t run, std::vector<uint32_t>* order) {
+  const uint32_t n = S.n;
+  std::vector<uint32_t> fill(kNumXcd, 0u);
+  order->assign(n, 0u);
+  for (uint32_t t = 0; t < n; ++t) {
+    uint32_t x = (t / run) % kNumXcd;
+    while (fill[x] == tile_xcd_count(n, x)) x = (x + 1) % kNumXcd;
+    (*order)[tile_xcd_start(n, x) + fill[x]++] = t;
+  }
 }
 
 template <int N>

@@ -4,18 +4,20 @@
 //
 // The arrival term A(m) = sum_j lambda_j/Lam V(m, j) is kept in an FP64 side
 // array written at the end of every sweep (the FMA chain the direct form
-// evaluates at m, in the same order, so the value is the same), and staged in
-// LDS with the tile's values: a placement along a low digit or the paid cloud
-// reads LDS, a placement along a high digit one global double.  The
-// placement offset size_e (C+1)^a of action a comes from lane a of a
-// per-class register table (one cross-lane read).
+// evaluates at m, in the same order, so the value is the same).  A state
+// reads the one arrival term its action needs straight from global memory
+// (one double; the tile's own block and its neighbours' are L2 hits): only
+// the values are staged in LDS, which keeps the image at 8J bytes per
+// occupancy and four workgroups per CU.  The placement offset size_e
+// (C+1)^a of action a comes from lane a of a per-class register table (one
+// cross-lane read).
 #include "kernels.hpp"
 #include "tile.hpp"
 
 namespace mdpvi {
 
 template <int K, int J, int T>
-__global__ __launch_bounds__(kBlock) void eval_tile_kernel(Model M, TileShape S, const uint8_t* __restrict__ pi,
+__global__ __launch_bounds__(kTileBlock, kTileMinWaves) void eval_tile_kernel(Model M, TileShape S, const uint8_t* __restrict__ pi,
                                                             const double* __restrict__ Vin,
                                                             double* __restrict__ Vout,
                                                             const double* __restrict__ Ain,
@@ -25,8 +27,7 @@ __global__ __launch_bounds__(kBlock) void eval_tile_kernel(Model M, TileShape S,
   constexpr int H = K - T;
   extern __shared__ double tile_lds[];
   const uint32_t occ = S.occ;
-  double* Al = tile_lds;            // [occ]
-  double* Vl = tile_lds + occ;      // [J][occ]
+  double* Vl = tile_lds;            // [J][occ]
   const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
   const uint32_t ns = static_cast<uint32_t>(M.n_states);
   const uint32_t cls = nocc * 8u;
@@ -37,15 +38,12 @@ __global__ __launch_bounds__(kBlock) void eval_tile_kernel(Model M, TileShape S,
   const BufView aout = make_view(Aout, nocc * 8u);
   double dmax = 0.0;
   const TileWalk tw = tile_walk(S);
-  for (uint32_t tb = tw.first; tb < tw.end; tb += tw.step) {
+  for (uint32_t tp = tw.first; tp < tw.end; tp += tw.step) {
+    const uint32_t tb = tile_at(S, tp);
   int nh[H];
   const uint32_t o0 = tile_high<K, T>(M, tb, nh);
 
-  for (uint32_t i = threadIdx.x; i < occ; i += kBlock) {
-#pragma unroll
-    for (int e = 0; e < J; ++e) Vl[e * occ + i] = ld_f64(vin, i * 8u, o0 * 8u + e * cls);
-    Al[i] = ld_f64(ain, i * 8u, o0 * 8u);
-  }
+  stage_values<J, kTileBlock>(occ, o0, cls, vin, Vl);
   __syncthreads();
 
   uint32_t hd8[H], hr8[H];
@@ -69,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void eval_tile_kernel(Model M, TileShape S,
     off_tab[e] = v;
   }
 
-  for (uint32_t i0 = 0; i0 < occ; i0 += kBlock) {
+  for (uint32_t i0 = 0; i0 < occ; i0 += kTileBlock) {
     // every lane takes part in the cross-lane reads; lanes past the tile
     // work on its last occupancy and store nothing
     const bool valid = i0 + threadIdx.x < occ;
@@ -90,14 +88,10 @@ __global__ __launch_bounds__(kBlock) void eval_tile_kernel(Model M, TileShape S,
     // arrival terms: placements along a high digit from global memory (the
     // other lanes load their own entry and use the LDS value)
     double ag[J];
-    uint32_t li[J];
-    bool high[J];
 #pragma unroll
     for (int e = 0; e < J; ++e) {
       const uint32_t off = static_cast<uint32_t>(__shfl(off_tab[e], a[e], kWave));
-      high[e] = a[e] >= T && a[e] < K;
-      ag[e] = ld_f64(ain, high[e] ? i8 + off * 8u : i8, o0 * 8u);
-      li[e] = a[e] < T ? i + off : i;
+      ag[e] = ld_f64(ain, a[e] < K ? i8 + off * 8u : i8, o0 * 8u);
     }
     int n[K];
     tile_low<T>(M, i, n);
@@ -133,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void eval_tile_kernel(Model M, TileShape S,
         rs += vr[k][e];
       }
       D = fma(M.nu_L, rs, D);
-      const double A = high[e] ? ag[e] : Al[li[e]];
+      const double A = ag[e];
       const double vn = fma(M.gamma, D, fma(M.gamma, A, r));
       anew = fma(M.p[e], vn, anew);
       if (valid) {
@@ -146,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void eval_tile_kernel(Model M, TileShape S,
   }
   __syncthreads();   // the next tile overwrites the LDS image
   }
-  block_max_to(dmax, ctl, res, j, tol);
+  block_max_to<kTileBlock>(dmax, ctl, res, j, tol);
 }
 
 // A(o) = sum_e lambda_e/Lam V(o, e) of an FP64 iterate (the FMA chain the
@@ -160,7 +154,7 @@ __global__ void eval_arrival_init_kernel(Model M, const double* __restrict__ V, 
 }
 
 bool eval_tile_shape(const Model& M, TileShape* S) {
-  return M.n_states < (int64_t{1} << 28) && tile_shape(M, 8u * M.J + 8u, kTileLds, S);
+  return M.n_states < (int64_t{1} << 28) && tile_shape(M, 8u * M.J, kTileLds, S);
 }
 
 hipError_t launch_eval_arrival_init(const Model& M, const double* V, double* A, hipStream_t s) {
@@ -172,10 +166,10 @@ hipError_t launch_eval_arrival_init(const Model& M, const double* V, double* A, 
 hipError_t launch_eval_tile(const Model& M, const TileShape& S, const uint8_t* pi, const double* Vin,
                             double* Vout, const double* Ain, double* Aout, Ctl* ctl, double* res, long long j,
                             double tol, hipStream_t s) {
-  const size_t lds = static_cast<size_t>(S.occ) * 8 * (M.J + 1);
+  const size_t lds = static_cast<size_t>(S.occ) * 8 * M.J;
   return tile_dispatch(M.K, M.J, S.T, [&](auto kc, auto jc, auto tc) {
     constexpr int Kc = decltype(kc)::value, Jc = decltype(jc)::value, Tc = decltype(tc)::value;
-    hipLaunchKernelGGL((eval_tile_kernel<Kc, Jc, Tc>), dim3(S.grid), dim3(kBlock), lds, s, M, S, pi, Vin, Vout,
+    hipLaunchKernelGGL((eval_tile_kernel<Kc, Jc, Tc>), dim3(S.grid), dim3(kTileBlock), lds, s, M, S, pi, Vin, Vout,
                        Ain, Aout, ctl, res, j, tol);
     return hipGetLastError();
   });

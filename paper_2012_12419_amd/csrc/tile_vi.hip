@@ -136,20 +136,15 @@ __device__ __forceinline__ void tile_backup(const Model& M, const TileHigh<K, J,
 
 // Stages the tile's values and arrival terms into (Vl, Al) and sets the
 // sentinel Al[occ] = -inf.
-template <int J>
+template <int J, int NB>
 __device__ __forceinline__ void tile_stage(const Model& M, uint32_t occ, uint32_t o0, BufView vin, BufView ain,
                                            float* Vl, double* Al) {
-  const uint32_t cls = static_cast<uint32_t>(M.n_occ) * 4u;
-  for (uint32_t i = threadIdx.x; i < occ; i += kBlock) {
-#pragma unroll
-    for (int e = 0; e < J; ++e) Vl[e * occ + i] = ld_f32(vin, i * 4u, o0 * 4u + e * cls);
-    Al[i] = ld_f64(ain, i * 8u, o0 * 8u);
-  }
+  stage_tile<J, NB, float>(occ, o0, static_cast<uint32_t>(M.n_occ) * 4u, vin, ain, Vl, Al);
   if (threadIdx.x == 0) Al[occ] = -INFINITY;
 }
 
 template <int K, int J, int T>
-__global__ __launch_bounds__(kBlock) void vi_tile_kernel(Model M, TileShape S, const float* __restrict__ Vin,
+__global__ __launch_bounds__(kTileBlock, kTileMinWaves) void vi_tile_kernel(Model M, TileShape S, const float* __restrict__ Vin,
                                                           float* __restrict__ Vout,
                                                           const double* __restrict__ Ain,
                                                           double* __restrict__ Aout, Ctl* ctl, double* res,
@@ -169,12 +164,13 @@ __global__ __launch_bounds__(kBlock) void vi_tile_kernel(Model M, TileShape S, c
   double dmax = 0.0;
   bool bad = false;
   const TileWalk tw = tile_walk(S);
-  for (uint32_t tb = tw.first; tb < tw.end; tb += tw.step) {
+  for (uint32_t tp = tw.first; tp < tw.end; tp += tw.step) {
+    const uint32_t tb = tile_at(S, tp);
     TileHigh<K, J, T> H;
     tile_high_setup<K, J, T>(M, tb, H);
-    tile_stage<J>(M, occ, H.o0, vin, ain, Vl, Al);
+    tile_stage<J, kTileBlock>(M, occ, H.o0, vin, ain, Vl, Al);
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < occ; i += kBlock) {
+    for (uint32_t i = threadIdx.x; i < occ; i += kTileBlock) {
       float vs[J], vn[J];
       double anew;
       tile_backup<K, J, T, false>(M, H, occ, Vl, Al, vin, ain, i, vs, vn, anew);
@@ -189,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void vi_tile_kernel(Model M, TileShape S, c
     }
     __syncthreads();   // the next tile overwrites the LDS image
   }
-  block_max_to(bad ? NAN : dmax, ctl, res, j, tol);
+  block_max_to<kTileBlock>(bad ? NAN : dmax, ctl, res, j, tol);
 }
 
 template <int K, int J, int T>
@@ -215,10 +211,11 @@ __global__ __launch_bounds__(kBlock) void vi_bsdi_kernel(Model M, TileShape S, i
   double dmax = 0.0;
   bool bad = false;
   const TileWalk tw = tile_walk(S);
-  for (uint32_t tb = tw.first; tb < tw.end; tb += tw.step) {
+  for (uint32_t tp = tw.first; tp < tw.end; tp += tw.step) {
+    const uint32_t tb = tile_at(S, tp);
     TileHigh<K, J, T> H;
     tile_high_setup<K, J, T>(M, tb, H);
-    tile_stage<J>(M, occ, H.o0, vin, ain, Vl[0], Al[0]);
+    tile_stage<J, kBlock>(M, occ, H.o0, vin, ain, Vl[0], Al[0]);
     if (threadIdx.x == 0) Al[1][occ] = -INFINITY;
     __syncthreads();
     for (int k = 0; k < inner; ++k) {
@@ -262,7 +259,7 @@ hipError_t launch_vi_tile(const Model& M, const TileShape& S, const float* Vin, 
   const size_t lds = static_cast<size_t>(S.occ + 1) * 8 + static_cast<size_t>(S.occ) * 4 * M.J;
   return tile_dispatch(M.K, M.J, S.T, [&](auto kc, auto jc, auto tc) {
     constexpr int Kc = decltype(kc)::value, Jc = decltype(jc)::value, Tc = decltype(tc)::value;
-    hipLaunchKernelGGL((vi_tile_kernel<Kc, Jc, Tc>), dim3(S.grid), dim3(kBlock), lds, s, M, S, Vin, Vout, Ain,
+    hipLaunchKernelGGL((vi_tile_kernel<Kc, Jc, Tc>), dim3(S.grid), dim3(kTileBlock), lds, s, M, S, Vin, Vout, Ain,
                        Aout, ctl, res, j, tol);
     return hipGetLastError();
   });
