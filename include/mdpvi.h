@@ -277,7 +277,12 @@ int vi_solve_bsdi(mdpvi_mdp_t h, float *V, double tol, int64_t max_iter, int32_t
  * 2..4 whose tile fits 48 KB of LDS); w = 0 launches one workgroup per
  * tile, w > 0 launches w workgroups per CU that walk their XCD's tiles in
  * order.  The automatic choice requires at least 256 occupancies per tile
- * and 256 tiles.
+ * and 256 tiles.  Tiles are handed to the XCDs in a host-computed order:
+ * recursive coordinate bisection of the tile grid when the sweep's working
+ * set fits 256 MB, runs of 16 tiles dealt round-robin beyond; the
+ * environment variable MDPVI_TILE_ORDER (read at every solve; a measurement
+ * aid) forces "index" (contiguous eighths), "rcb" or "dealN" (runs of N).
+ * Every order and every w give bit-identical iterates.
  * Automatic mode uses the tile form where it applies, unless mdp_autotune
  * recorded another form for the shape, then the exact-shape direct form,
  * then the slab form.  Errors: MDPVI_EINVAL (NULL handle, t >= K, a slab

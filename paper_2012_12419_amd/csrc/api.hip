@@ -250,10 +250,8 @@ constexpr uint32_t kDealRun = 16;
 // overrides the choice: "index" (contiguous eighths of the index order),
 // "rcb", or "dealN" (runs of N tiles dealt round-robin).
 int set_tile_order(mdpvi_mdp* h, mdpvi::TileShape* S, double ws) {
-  static const std::string forced = [] {
-    const char* e = std::getenv("MDPVI_TILE_ORDER");
-    return std::string(e ? e : "");
-  }();
+  const char* env = std::getenv("MDPVI_TILE_ORDER");
+  const std::string forced(env ? env : "");
   S->order = nullptr;
   if (forced == "index") return MDPVI_OK;
   if (S->T < 2 || S->T > 4) return fail(MDPVI_EINVAL, "tile depth %d outside [2, 4]", S->T);

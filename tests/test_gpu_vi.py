@@ -339,6 +339,48 @@ def test_tile_full_size_matches_direct(mdpvi):
         assert np.array_equal(outs[0][1], outs[f][1])
 
 
+def test_tile_orders_bit_identical(mdpvi):
+    # every tile order (contiguous eighths, coordinate bisection, dealt runs)
+    # and walker count runs the same per-state arithmetic: same bits as the
+    # direct form on the 5.3M-state instance
+    import os
+    import torch
+    inst = W.large_single()
+    ref = None
+    cases = [(None, 0), ("index", mdpvi.FORM_TILE), ("rcb", mdpvi.FORM_TILE), ("deal1", mdpvi.FORM_TILE),
+             ("deal16", mdpvi.FORM_TILE), ("deal7", mdpvi.FORM_TILE + 3), ("rcb", mdpvi.FORM_TILE + 2)]
+    old = os.environ.get("MDPVI_TILE_ORDER")
+    try:
+        for order, form in cases:
+            if order is None:
+                os.environ.pop("MDPVI_TILE_ORDER", None)
+            else:
+                os.environ["MDPVI_TILE_ORDER"] = order
+            mdp = mdpvi.MDP.from_instance(inst)
+            mdp.set_sweep_form(form)
+            pi = mdp.policy_greedy("least_loaded")
+            V = torch.zeros(mdp.num_states, device="cuda")
+            with pytest.raises(mdpvi.MdpviError) as ei:
+                mdp.vi_solve(V, tol=1e-30, max_iter=12)
+            assert ei.value.code == mdpvi.ENOCONV
+            Ve = torch.zeros(mdp.num_states, dtype=torch.float64, device="cuda")
+            with pytest.raises(mdpvi.MdpviError) as ei:
+                mdp.policy_eval(pi, Ve, tol=1e-30, max_iter=12)
+            assert ei.value.code == mdpvi.ENOCONV
+            got = (V.cpu().numpy().view(np.uint32).copy(), Ve.cpu().numpy().view(np.uint64).copy())
+            print(f"large_single order {order} form {form}: done", flush=True)
+            if ref is None:
+                ref = got
+            else:
+                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+            del mdp
+    finally:
+        if old is None:
+            os.environ.pop("MDPVI_TILE_ORDER", None)
+        else:
+            os.environ["MDPVI_TILE_ORDER"] = old
+
+
 def test_autotune_cache(mdpvi, tmp_path):
     import json
     import os
