@@ -19,10 +19,10 @@ value = state-action backups per second over the timed steps: feasible
 backup per state per fixed-policy sweep, divided by the wall time of the
 steps.  The JSON line also carries the time to ||dV||_inf < 1e-6, the
 roofline of the dominant kernel (algorithmic bytes per launch over the
-average launch duration; the durations come from one extra step, outside
-the timed ones, in which HIP events bracket every sweep on the solver's
-stream) and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+average launch duration: the timed solves' spans between the HIP events the
+library records on the solver's stream, over their working sweeps; one
+extra step with an event pair around every sweep is reported beside it) and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -362,8 +362,9 @@ def main() -> int:
         except mdpvi.MdpviError as e:
             bsdi = {"skipped": str(e)}
 
-    # one more step with every sweep bracketed by HIP events on the solver's
-    # stream (outside the timed region): per-kernel durations
+    # one more step with every sweep bracketed by its own pair of HIP events
+    # (outside the timed region): a cross-check of the per-launch durations,
+    # which the event pairs inflate by their own cost
     meas = None
     if not args.no_timing:
         mdp.set_timing(True)
@@ -386,7 +387,7 @@ def main() -> int:
 
     roof = None
     kernels = {}
-    if meas is not None:
+    if recs:
         tile = 16
         vi_impl = ("vi_tile_kernel" if vi_form >= tile else
                    "vi_slab_kernel" if vi_form > 0 else "vi_exact_kernel")
@@ -400,18 +401,27 @@ def main() -> int:
                                      "paper_2012_12419_amd/csrc/tile.hpp"],
                 "eval_exact_kernel": ["paper_2012_12419_amd/csrc/policy.hip",
                                       "paper_2012_12419_amd/csrc/policy_impl.hpp"]}
-        n_vi = meas[0]["iterations"]
-        n_ev = meas[1]["iterations"] + meas[2]["iterations"]
-        t_meas = meas[0]["seconds"] + meas[1]["seconds"] + meas[2]["seconds"]
-        for name, impl, tot, cnt, bps in [
-                ("vi_sweep_kernel", vi_impl, meas[0]["sweep_seconds"], n_vi, VI_BYTES_PER_STATE),
-                ("eval_sweep_kernel", ev_impl, meas[1]["sweep_seconds"] + meas[2]["sweep_seconds"], n_ev,
-                 EVAL_BYTES_PER_STATE)]:
+        # per-launch duration over the timed steps: each solve's span between
+        # the HIP events that the library records on the solver's stream
+        # before its first and after its last sweep, divided by the sweeps
+        # that did work (the span also holds the few launches issued after
+        # the stopping test and the per-chunk control reads: an upper bound)
+        n_vi = sum(r[0]["iterations"] for r in recs)
+        n_ev = sum(r[1]["iterations"] + r[2]["iterations"] for r in recs)
+        t_vi = sum(r[0]["seconds"] for r in recs)
+        t_ev = sum(r[1]["seconds"] + r[2]["seconds"] for r in recs)
+        for name, impl, tot, cnt, bps, bracketed in [
+                ("vi_sweep_kernel", vi_impl, t_vi, n_vi, VI_BYTES_PER_STATE,
+                 (meas[0]["sweep_seconds"], meas[0]["iterations"]) if meas else None),
+                ("eval_sweep_kernel", ev_impl, t_ev, n_ev, EVAL_BYTES_PER_STATE,
+                 (meas[1]["sweep_seconds"] + meas[2]["sweep_seconds"],
+                  meas[1]["iterations"] + meas[2]["iterations"]) if meas else None)]:
             avg = tot / cnt
             ach = bps * N / avg / 1e9
             kernels[name] = {"kernel": impl, "launches": cnt, "avg_us": avg * 1e6, "bytes_per_launch": bps * N,
                              "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
-                             "share_of_solve_time": tot / t_meas,
+                             "share_of_solve_time": tot / (t_vi + t_ev),
+                             "avg_us_event_pair_per_sweep": bracketed[0] / bracketed[1] * 1e6 if bracketed else None,
                              "traffic": traffic_record(srcs[impl], f"{impl}_{args.workload}")}
         dom = max(kernels, key=lambda k: kernels[k]["share_of_solve_time"])
         kd = kernels[dom]
