@@ -29,17 +29,19 @@
 
 namespace mdpvi {
 
-template <int KMAX, int JMAX, typename Idx>
+// OPT occupancies per thread: 1 below kAdjointWideOcc occupancies, so that a
+// small instance still spreads over every CU; kOccPerThread above.
+template <int KMAX, int JMAX, typename Idx, int OPT>
 __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(Model M, const uint8_t* __restrict__ pi,
                                                                 const float* __restrict__ win,
                                                                 float* __restrict__ wout, Ctl* ctl,
                                                                 double* res, long long j, double tol) {
   if (sweep_stopped<ResKind::kSum>(ctl, res, j, tol)) return;
   const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-  const Idx base = static_cast<Idx>(b) * (kBlock * kOccPerThread) + threadIdx.x;
+  const Idx base = static_cast<Idx>(b) * (kBlock * OPT) + threadIdx.x;
   double dsum = 0.0;
 #pragma unroll
-  for (int i = 0; i < kOccPerThread; ++i) {
+  for (int i = 0; i < OPT; ++i) {
     const Idx o = base + static_cast<Idx>(i * kBlock);
     if (o < static_cast<Idx>(M.n_occ)) dsum += adjoint_occupancy<KMAX, JMAX>(M, pi, win, wout, o);
   }
@@ -156,6 +158,16 @@ static inline uint32_t sweep_blocks(const Model& M) {
   return static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + per - 1) / per);
 }
 
+// Below this many occupancies the adjoint sweep takes one occupancy per
+// thread (at 161,051 occupancies four per thread leave 158 workgroups for
+// 256 CUs).
+constexpr int64_t kAdjointWideOcc = int64_t{2} << 20;
+
+static inline uint32_t adjoint_blocks(const Model& M, int opt) {
+  const uint64_t per = static_cast<uint64_t>(kBlock) * static_cast<uint64_t>(opt);
+  return static_cast<uint32_t>((static_cast<uint64_t>(M.n_occ) + per - 1) / per);
+}
+
 size_t grad_partial_doubles(const Model& M) {
   return static_cast<size_t>(sweep_blocks(M)) * (2 * (M.J <= 4 ? 4 : 8) + 2);
 }
@@ -164,12 +176,17 @@ hipError_t launch_adjoint_sweep(const Model& M, const uint8_t* pi, const float* 
                                 Ctl* ctl, double* res, long long j, double tol, hipStream_t s) {
   return dispatch_kj(M, [&](auto km, auto jm) {
     constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
-    if (use_32bit_index(M)) {
-      hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint32_t>), dim3(sweep_blocks(M)), dim3(kBlock),
+    if (M.n_occ < kAdjointWideOcc) {
+      hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint32_t, 1>), dim3(adjoint_blocks(M, 1)), dim3(kBlock),
                          0, s, M, pi, win, wout, ctl, res, j, tol);
+    } else if (use_32bit_index(M)) {
+      hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint32_t, kOccPerThread>),
+                         dim3(adjoint_blocks(M, kOccPerThread)), dim3(kBlock), 0, s, M, pi, win, wout, ctl, res,
+                         j, tol);
     } else {
-      hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint64_t>), dim3(sweep_blocks(M)), dim3(kBlock),
-                         0, s, M, pi, win, wout, ctl, res, j, tol);
+      hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint64_t, kOccPerThread>),
+                         dim3(adjoint_blocks(M, kOccPerThread)), dim3(kBlock), 0, s, M, pi, win, wout, ctl, res,
+                         j, tol);
     }
     return hipGetLastError();
   });
