@@ -14,6 +14,10 @@
         --kernel vi_exact_kernel --name vi_sweep_kernel_large_single \
         --copy-bytes 1073741824 --sources <files...> --command "..."
 
+    # per-dispatch medians of any counters, one or more --pmc runs per kernel
+    python -m paper_2012_12419_amd.profiling counters --dirs <dir...> \
+        --kernels vi_tile_kernel eval_tile_kernel --command "..." > profiles/X.md
+
 The traffic record carries a SHA-256 of the kernel's source files; bench.py
 reports the traffic only while the sources are unchanged.
 """
@@ -163,6 +167,33 @@ def run_sweeps(kernel: str, workload: str, sweeps: int, copy_mb: int, form: int)
     print(f"ran {sweeps} {kernel} sweeps on {workload}, copy {copy_mb} MiB", flush=True)
 
 
+def counters_markdown(dirs, kernels, command: str) -> str:
+    """Median over dispatches of every counter found in the --pmc output
+    directories, per kernel (a kernel name matches when it contains the given
+    string), as a markdown table with one row per counter."""
+    rows = []
+    for d in dirs:
+        rows += _counter_rows(d)
+    names = sorted({r["Counter_Name"] for r in rows})
+    table = {}
+    for k in kernels:
+        for c in names:
+            v = _per_dispatch(rows, c, lambda n, k=k: k in n)
+            if v:
+                table[(c, k)] = (statistics.median(v), len(v))
+    out = [f"Command: `{command}`", "", "Per-dispatch medians (dispatches in brackets).", "",
+           "| Counter | " + " | ".join(f"`{k}`" for k in kernels) + " |",
+           "|---|" + "---|" * len(kernels)]
+    for c in names:
+        cells = []
+        for k in kernels:
+            m = table.get((c, k))
+            cells.append(f"{m[0]:.4g} ({m[1]})" if m else "")
+        if any(cells):
+            out.append(f"| {c} | " + " | ".join(cells) + " |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -177,6 +208,10 @@ def main(argv=None) -> int:
     s.add_argument("--command", required=True)
     s.add_argument("--trace", default=None, help="kernel_trace.csv of the same run")
     s.add_argument("--kernels", nargs="*", default=[], help="kernels to list working launches of")
+    c = sub.add_parser("counters")
+    c.add_argument("--dirs", nargs="+", required=True)
+    c.add_argument("--kernels", nargs="+", required=True)
+    c.add_argument("--command", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -191,6 +226,9 @@ def main(argv=None) -> int:
         return 0
     if a.cmd == "stats":
         sys.stdout.write(stats_markdown(a.csv, a.command, trace_csv=a.trace, kernels=a.kernels))
+        return 0
+    if a.cmd == "counters":
+        sys.stdout.write(counters_markdown(a.dirs, a.kernels, a.command))
         return 0
     rec = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.sources, a.command)
     path = os.path.join(ROOT, "profiles", f"{a.name}_traffic.json")
