@@ -347,8 +347,10 @@ def test_tile_orders_bit_identical(mdpvi):
     import torch
     inst = W.large_single()
     ref = None
-    cases = [(None, 0), ("index", mdpvi.FORM_TILE), ("rcb", mdpvi.FORM_TILE), ("deal1", mdpvi.FORM_TILE),
-             ("deal16", mdpvi.FORM_TILE), ("deal7", mdpvi.FORM_TILE + 3), ("rcb", mdpvi.FORM_TILE + 2)]
+    # (None, -1): the automatic choice, the launch configuration bench.py times
+    cases = [(None, 0), (None, -1), ("index", mdpvi.FORM_TILE), ("rcb", mdpvi.FORM_TILE),
+             ("deal1", mdpvi.FORM_TILE), ("deal16", mdpvi.FORM_TILE), ("deal7", mdpvi.FORM_TILE + 3),
+             ("rcb", mdpvi.FORM_TILE + 2)]
     old = os.environ.get("MDPVI_TILE_ORDER")
     try:
         for order, form in cases:
@@ -368,7 +370,7 @@ def test_tile_orders_bit_identical(mdpvi):
                 mdp.policy_eval(pi, Ve, tol=1e-30, max_iter=12)
             assert ei.value.code == mdpvi.ENOCONV
             got = (V.cpu().numpy().view(np.uint32).copy(), Ve.cpu().numpy().view(np.uint64).copy())
-            print(f"large_single order {order} form {form}: done", flush=True)
+            print(f"large_single order {order} form {form} (runs {mdp.sweep_forms()}): done", flush=True)
             if ref is None:
                 ref = got
             else:
