@@ -339,6 +339,50 @@ def test_tile_full_size_matches_direct(mdpvi):
         assert np.array_equal(outs[0][1], outs[f][1])
 
 
+def test_k7_beyond_cache_sampled(mdpvi):
+    # the 58,461,513-state instance (K = 7; one workgroup per tile, runs of
+    # tiles dealt round-robin): at sampled states the GPU values are a fixed
+    # point of the oracle's per-state Bellman backup up to half an FP32 ulp
+    # (plus the stopping error), the extracted policy is the oracle's argmax
+    # where it is clear, and the FP64 evaluation of the least-loaded policy
+    # satisfies its fixed-policy equation to 1e-10 relative
+    import torch
+    inst = W.large_single(K=7)
+    mdp = mdpvi.MDP.from_instance(inst)
+    V = torch.zeros(mdp.num_states, device="cuda")
+    st = mdp.vi_solve(V, tol=1e-6)
+    print(f"K=7: {st['iterations']} sweeps, {st['seconds']:.3f} s, forms {mdp.sweep_forms()}", flush=True)
+    pi, _ = mdp.policy_extract(V, want_gap=False)
+    Vg = V.cpu().numpy().astype(np.float64)
+    pi = pi.cpu().numpy()
+    del V
+    rng = np.random.default_rng(7)
+    samples = np.concatenate([rng.integers(0, mdp.num_states, 800), [0, mdp.num_states - 1]])
+    scale = np.max(np.abs(Vg))
+    for s_ in samples:
+        s_ = int(s_)
+        best, arg, qs = model.bellman_backup(inst, Vg, s_)
+        half_ulp = float(np.spacing(np.float32(abs(Vg[s_])))) / 2
+        # stopped at ||dV|| < 1e-6: |T V - V| <= gamma 1e-6 + one FP32 rounding
+        assert abs(best - Vg[s_]) <= 1.0001 * half_ulp + 1e-6, s_
+        srt = sorted(qs)
+        if len(qs) == 1 or (srt[-1] - srt[-2]) > 1e-6 * max(abs(best), 1e-3 * scale):
+            assert pi[s_] == arg, (s_, pi[s_], arg)
+    pig = mdp.policy_greedy("least_loaded")
+    Ve = torch.zeros(mdp.num_states, dtype=torch.float64, device="cuda")
+    _, st2 = mdp.policy_eval(pig, Ve, tol=1e-11)
+    print(f"K=7 evaluation: {st2['iterations']} sweeps, {st2['seconds']:.3f} s", flush=True)
+    Vh = Ve.cpu().numpy()
+    pg = pig.cpu().numpy()
+    del Ve
+    for s_ in samples:
+        s_ = int(s_)
+        acts = model.feasible_actions(inst, s_)
+        _, _, qs = model.bellman_backup(inst, Vh, s_)
+        q = qs[acts.index(int(pg[s_]))]
+        assert abs(q - Vh[s_]) <= 1e-10 * np.max(np.abs(Vh)) + inst.gamma / (1 - inst.gamma) * 1e-11, s_
+
+
 def test_tile_orders_bit_identical(mdpvi):
     # every tile order (contiguous eighths, coordinate bisection, dealt runs)
     # and walker count runs the same per-state arithmetic: same bits as the
