@@ -26,8 +26,11 @@ here are:
 * Reward, Sec. V-E Eqs. (14)-(16): R(e, place) = r_e (the VC reward net of
   its cost), R(e, reject) = -c_e (the paid-cloud cost).  It accrues on the
   arrival branch only, so the expected one-step reward is P_arr R(e, a),
-  P_arr = sum_j lambda_j / Lam.  The paper's under-utilisation penalty is not
-  part of this model.
+  P_arr = sum_j lambda_j / Lam.  The under-utilisation penalty of Eq. (16)
+  (the paper's gamma_vc times the free VMs) is read as a cost
+  ``idle_unit_cost`` u per free VM unit of every host, charged on every
+  uniformised step: r(s, a) = P_arr R(e, a) - u (K C - sum_k n_k).  Every
+  benchmark workload has u = 0.
 * Bellman, Sec. V-G Eq. (18): with a discount gamma per uniformised step,
   Q(s,a) = r(s,a) + gamma sum_s' P(s'|s,a) V(s'), V(s) = max over feasible a.
 """

@@ -23,7 +23,8 @@ class MdpValue(torch.autograd.Function):
     def forward(ctx, lam, mu, nu, reward, spec):
         K, C, size, gamma = spec["K"], spec["C"], spec["size"], spec["gamma"]
         mdp = MDP(K, C, size, lam.detach().double().cpu().tolist(), float(mu), float(nu),
-                  reward.detach().double().cpu().tolist(), gamma, spec.get("reject_cost"))
+                  reward.detach().double().cpu().tolist(), gamma, spec.get("reject_cost"),
+                  spec.get("idle_unit_cost", 0.0))
         dev = spec.get("device", "cuda")
         V = torch.zeros(mdp.num_states, dtype=torch.float32, device=dev)
         if spec.get("V0") is not None:
@@ -57,7 +58,15 @@ class MdpValue(torch.autograd.Function):
 
 def expected_reward(lam: torch.Tensor, mu: torch.Tensor, nu: torch.Tensor, reward: torch.Tensor,
                     K: int, C: int, size: Sequence[int], gamma: float,
-                    reject_cost: Optional[Sequence[float]] = None, **opts) -> torch.Tensor:
-    """Optimal J(lambda, mu, nu, r) as a differentiable scalar tensor."""
-    spec = dict(K=K, C=C, size=list(size), gamma=gamma, reject_cost=reject_cost, **opts)
+                    reject_cost: Optional[Sequence[float]] = None, idle_unit_cost: float = 0.0,
+                    **opts) -> torch.Tensor:
+    """Optimal J(lambda, mu, nu, r) as a differentiable scalar tensor.  The
+    paid-cloud costs and the under-utilisation penalty per free unit are held
+    fixed (not differentiated)."""
+    known = {"tol", "eval_tol", "adjoint_tol", "improve_steps", "device", "V0"}
+    unknown = set(opts) - known
+    if unknown:
+        raise TypeError(f"unknown options {sorted(unknown)}")
+    spec = dict(K=K, C=C, size=list(size), gamma=gamma, reject_cost=reject_cost,
+                idle_unit_cost=float(idle_unit_cost), **opts)
     return MdpValue.apply(lam, mu, nu, reward, spec)

@@ -152,11 +152,14 @@ inline void tile_partition(int K, int R, const TileShape& S, std::vector<uint32_
 
 // The deepest tile (T in 2..min(4, K-1)) whose LDS footprint of
 // bytes_per_occ bytes per occupancy fits lds_limit (and, for the -inf
-// sentinel block, at most kSentinel occupancies); false if none, or if the
-// shape is not an exact one (K in 3..8, J <= 3 distinct sizes).
+// sentinel block, at most kSentinel occupancies); false if none, if the
+// shape is not an exact one (K in 3..8, J <= 3 distinct sizes), or if the
+// value array reaches 2 GiB (2^29 FP32 states).
 inline bool tile_shape(const Model& M, uint32_t bytes_per_occ, uint32_t lds_limit, TileShape* S) {
   if (M.K < 3 || M.K > 8 || M.J < 1 || M.J > 3 || M.n_sizes != M.J) return false;
-  if (M.n_occ + kSentinel >= (int64_t{1} << 28)) return false;
+  // buffer views hold byte offsets below 2^31: the FP32 values (n_states
+  // words) and the FP64 arrival terms with their sentinel block
+  if (M.n_states >= (int64_t{1} << 29) || M.n_occ + kSentinel >= (int64_t{1} << 28)) return false;
   for (int T = (M.K - 1 < 4 ? M.K - 1 : 4); T >= 2; --T) {
     uint64_t occ = 1;
     for (int i = 0; i < T; ++i) occ *= static_cast<uint64_t>(M.R);

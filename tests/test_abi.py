@@ -102,3 +102,27 @@ def test_python_binding_refuses_cpu_tensors():
     m = mdpvi.MDP(3, 8, [1, 2], [0.6, 0.3], 0.1, 0.02, [1.0, 2.5], 0.95)
     with pytest.raises(ValueError, match="GPU tensor"):
         m.vi_solve(torch.zeros(m.num_states))
+
+
+@pytest.mark.parametrize("K,C,J", [(8, 10, 3), (6, 24, 3), (7, 10, 3), (6, 10, 3)])
+def test_tile_form_only_below_2gib_values(K, C, J):
+    """The tile kernels address the FP32 values through 32-bit buffer offsets,
+    so the automatic choice (and an explicit request) must not take the tile
+    form once J (C+1)^K reaches 2^29 states.  Host-only: mdp_build and the
+    form query launch nothing."""
+    rc, h = _build(K=K, C=C, size=list(range(1, J + 1)), lam=[0.5] * J, reward=[1.0] * J)
+    assert rc == mdpvi.OK
+    lib = mdpvi.load()
+    try:
+        n = lib.mdp_num_states(h)
+        assert n == J * (C + 1) ** K
+        vi_f, ev_f = ctypes.c_int32(), ctypes.c_int32()
+        assert lib.mdp_sweep_forms(h, ctypes.byref(vi_f), ctypes.byref(ev_f)) == mdpvi.OK
+        is_tile = lambda f: mdpvi.FORM_TILE <= f <= mdpvi.FORM_TILE + 8
+        if n >= 2 ** 29:
+            assert not is_tile(vi_f.value) and not is_tile(ev_f.value)
+            assert lib.mdp_set_sweep_form(h, mdpvi.FORM_TILE) == mdpvi.EINVAL
+        else:
+            assert is_tile(vi_f.value)
+    finally:
+        lib.mdp_free(h)

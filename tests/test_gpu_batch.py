@@ -4,7 +4,7 @@
   the FP64 oracle instance by instance.
 * The 512-instance parameter sweep: every instance's batched result equals
   the single-instance vi_solve result bit for bit (same backup arithmetic, same
-  stopping test), and sampled instances are fixed points of the oracle's
+  stopping test), and every instance is a fixed point of the oracle's
   Bellman operator up to one FP32 rounding.
 """
 import numpy as np
@@ -62,6 +62,11 @@ def test_batch_mixed_vs_oracle(mdpvi):
 
 
 def test_batch_equals_per_instance(mdpvi):
+    """All 512 instances of the parameter sweep: the batched iterate equals the
+    single-instance vi_solve iterate bit for bit, with the same sweep count,
+    and every instance is a fixed point of the oracle's Bellman operator up
+    to half an FP32 ulp plus the stopping residual (one vectorised oracle
+    sweep per instance), which bounds ||V - V*|| by that over (1 - gamma)."""
     import torch
     insts = W.batch(512, seed=3)
     b = mdpvi.Batch(insts)
@@ -69,19 +74,18 @@ def test_batch_equals_per_instance(mdpvi):
     st, its, res = b.vi_solve(V, tol=1e-6)
     print(f"batch: {b.n} instances, {b.num_states} states, {st['seconds']:.3f} s", flush=True)
     Vh = V.cpu().numpy()
-    rng = np.random.default_rng(0)
-    check = set(rng.choice(512, 48, replace=False).tolist()) | {int(np.argmax([p.num_states for p in insts]))}
-    for i in sorted(check):
-        p = insts[i]
+    worst = 0.0
+    for i, p in enumerate(insts):
         mdp = mdpvi.MDP.from_instance(p)
         Vi = torch.zeros(mdp.num_states, device="cuda")
         sti = mdp.vi_solve(Vi, tol=1e-6)
         assert sti["iterations"] == its[i], (i, sti["iterations"], its[i])
         got = Vh[b.offsets[i]:b.offsets[i + 1]]
         assert np.array_equal(got.view(np.uint32), Vi.cpu().numpy().view(np.uint32)), i
-    for i in sorted(check)[:8]:
-        p = insts[i]
-        Vg = Vh[b.offsets[i]:b.offsets[i + 1]].astype(np.float64)
+        Vg = got.astype(np.float64)
         TV = vi.bellman(p, Vg)
-        half_ulp = np.spacing(np.abs(Vg).astype(np.float32)).astype(np.float64) / 2
-        assert np.all(np.abs(TV - Vg) <= 1.0001 * half_ulp + 1e-6)
+        half_ulp = np.spacing(np.abs(got)).astype(np.float64) / 2
+        excess = np.max(np.abs(TV - Vg) - 1.0001 * half_ulp)
+        assert excess <= 1e-6, (i, p.K, p.C, p.J, excess)
+        worst = max(worst, excess)
+    print(f"all 512 bit-identical; largest fixed-point excess over half an ulp {worst:.2e}", flush=True)

@@ -43,6 +43,7 @@ def _batch_pipeline(mdpvi, insts):
         lb[b.offsets[i]:b.offsets[i + 1]] = sub_solution(p)
     V.copy_(lb)
     b.vi_solve(V, tol=1e-7)
+    _batch_pipeline.last_V = V
     pi, _ = b.policy_extract(V, want_gap=False)
     Vp = V.double()
     # FP64 policy-iteration steps from the FP32 greedy policy until it is stable
@@ -98,3 +99,78 @@ def test_batch_gradient_equals_single_instance(mdpvi):
         assert np.array_equal(w1.cpu().numpy().view(np.uint32), w[sl].cpu().numpy().view(np.uint32)), i
         V1, _ = mdp.policy_eval(pig[sl].contiguous(), tol=1e-12)
         assert np.array_equal(V1.cpu().numpy().view(np.uint64), Vg[sl].cpu().numpy().view(np.uint64)), i
+
+
+def _eval_residual(p, pi, V):
+    """||r_pi + gamma P_pi V - V||_inf with the oracle's P_pi and r_pi."""
+    P, r = vi.policy_system(p, pi)
+    V = np.asarray(V, dtype=np.float64)
+    return np.max(np.abs(r + p.gamma * (P @ V) - V))
+
+
+def _adjoint_residual(p, pi, w):
+    P, _ = vi.policy_system(p, pi)
+    n_occ = (p.C + 1) ** p.K
+    c = np.zeros(P.shape[0])
+    lam = np.asarray(p.lam)
+    c[np.arange(p.J) * n_occ] = lam / lam.sum()
+    w = np.asarray(w, dtype=np.float64)
+    return np.abs(c + p.gamma * (P.T @ w) - w).sum()
+
+
+@pytest.mark.timeout(900)
+def test_batch_pipeline_first_256_of_sweep(mdpvi):
+    """The batched gradient and greedy-scoring pipeline on the first 256
+    instances of the 512-instance parameter sweep (the bench workload):
+
+    * every instance's gradient, adjoint weights, greedy policy and greedy
+      FP64 value equal the single-instance entry points' bit for bit;
+    * every instance's values are a fixed point of the oracle's Bellman
+      operator (half an FP32 ulp plus the stopping residual); its FP64 policy
+      value satisfies the oracle's fixed-policy equation to 1e-10 relative;
+      its policy is greedy with respect to that value under the oracle's Q
+      (so it is optimal); its adjoint weights satisfy the adjoint equation;
+    * the instances of at most 10,000 states (158 of them) against the
+      oracle's full pipeline: policy on the parity gap mask, FP64 value,
+      objective, gradient, greedy policy and its value."""
+    import torch
+
+    from tests.oracle_pool import batch_oracle
+    insts = W.batch(512, seed=3)[:256]
+    small = [i for i, p in enumerate(insts) if p.num_states <= 10_000]
+    b, pi, Vp, grads, objs, w, pig, Vg = _batch_pipeline(mdpvi, insts)
+    V32 = _batch_pipeline.last_V.cpu().numpy()
+    pi_h, Vp_h, pig_h, Vg_h, w_h = (t.cpu().numpy() for t in (pi, Vp, pig, Vg, w))
+    for i, p in enumerate(insts):
+        sl = slice(b.offsets[i], b.offsets[i + 1])
+        mdp = mdpvi.MDP.from_instance(p)
+        g1, J1, w1, _ = mdp.vi_adjoint(pi[sl].contiguous(), Vp[sl].contiguous(), tol=1e-11)
+        assert np.array_equal(np.array(g1), np.array(grads[i])), i
+        assert np.array_equal(w1.cpu().numpy().view(np.uint32), w_h[sl].view(np.uint32)), i
+        pg1 = mdp.policy_greedy("least_loaded")
+        assert np.array_equal(pg1.cpu().numpy(), pig_h[sl]), i
+        V1, _ = mdp.policy_eval(pig[sl].contiguous(), tol=1e-12)
+        assert np.array_equal(V1.cpu().numpy().view(np.uint64), Vg_h[sl].view(np.uint64)), i
+        # properties at any size, with the oracle's operators
+        v = V32[sl].astype(np.float64)
+        half_ulp = np.spacing(np.abs(V32[sl])).astype(np.float64) / 2
+        assert np.max(np.abs(vi.bellman(p, v) - v) - 1.0001 * half_ulp) <= 1e-7, i
+        scale = np.max(np.abs(Vp_h[sl]))
+        assert _eval_residual(p, pi_h[sl], Vp_h[sl]) <= 1e-10 * scale, i
+        Q = vi.q_table(p, Vp_h[sl])
+        chosen = Q[np.arange(p.num_states), pi_h[sl].astype(np.int64)]
+        assert np.all(chosen >= Q.max(axis=1) - 1e-9 * scale), i
+        assert _adjoint_residual(p, pi_h[sl], w_h[sl]) <= 1e-6 * np.abs(w_h[sl]).sum(), i
+        assert _eval_residual(p, pig_h[sl], Vg_h[sl]) <= 1e-10 * np.max(np.abs(Vg_h[sl])), i
+    print(f"256 instances: single-instance bit identity and oracle properties hold; "
+          f"oracle pipeline on {len(small)} instances", flush=True)
+    ref = batch_oracle(small, 512, 3)
+    for i in small:
+        p, o = insts[i], ref[i]
+        sl = slice(b.offsets[i], b.offsets[i + 1])
+        assert np.array_equal(pi_h[sl][o["mask"]], o["pi"][o["mask"]]), i
+        assert np.max(np.abs(Vp_h[sl] - o["V"])) <= EVAL_REL * np.max(np.abs(o["V"])), i
+        assert abs(objs[i] - o["J"]) <= 1e-10 * max(1.0, abs(o["J"])), i
+        assert np.max(np.abs(np.array(grads[i]) - o["grad"])) <= 1e-5 * np.max(np.abs(o["grad"])), i
+        assert np.array_equal(pig_h[sl], o["greedy"]), i
+        assert np.max(np.abs(Vg_h[sl] - o["V_greedy"])) <= EVAL_REL * np.max(np.abs(o["V_greedy"])), i
