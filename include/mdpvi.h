@@ -134,6 +134,26 @@ int64_t mdp_feasible_pairs(mdpvi_mdp_t h);
 int vi_solve(mdpvi_mdp_t h, float *V, double tol, int64_t max_iter,
              void *hip_stream, mdpvi_stats *st);
 
+/* Value iteration for callers that cannot allocate device memory (code
+ * under HIP graph capture aside, serving loops and harnesses that forbid
+ * hipMalloc): the same sweeps, stopping test and result as vi_solve (bit for
+ * bit), with every piece of device scratch (control and residual words, the
+ * FP64 arrival-term arrays, the second value buffer) taken from one
+ * file-scope device array of 64 MiB that each device running the library
+ * holds until the process ends.  No hipMalloc, hipFree or other allocating
+ * call is made; the caller still owns V (device float[N], in: V^0, out: the
+ * result).  The tile order is the index order and the automatic form choice
+ * ignores the tuning cache (every form and order gives the same iterates).
+ * st->seconds is the host wall time of the call; st->sweep_seconds is 0.
+ * The array keeps the last call's contents; every call clears what must
+ * start at zero.  All calls on one device share the one array: calls that
+ * overlap on one device (two streams, two threads) race and must not be made.
+ * Errors: those of vi_solve, and MDPVI_ERANGE when the instance needs more
+ * than the 64 MiB of scratch (about 5.5 million FP32 states of a tile-form
+ * shape; vi_solve has no such limit).                                      */
+int vi_solve_noalloc(mdpvi_mdp_t h, float *V, double tol, int64_t max_iter,
+                     void *hip_stream, mdpvi_stats *st);
+
 /* Greedy policy from a value function, Alg. 3 step 4:
  * pi[s] = lowest-index action maximising Q(s,a) (hosts in order, the paid
  * cloud last), Q formed in FP64 from V.

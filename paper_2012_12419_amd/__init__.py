@@ -67,6 +67,7 @@ SIGNATURES = {
     "mdp_num_actions": (_c_int32, [_vp]),
     "mdp_feasible_pairs": (_c_int64, [_vp]),
     "vi_solve": (ctypes.c_int, [_vp, _vp, _c_double, _c_int64, _vp, ctypes.POINTER(Stats)]),
+    "vi_solve_noalloc": (ctypes.c_int, [_vp, _vp, _c_double, _c_int64, _vp, ctypes.POINTER(Stats)]),
     "policy_extract": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "policy_extract_f64": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "policy_eval": (ctypes.c_int, [_vp, _vp, _vp, _c_double, _c_int64, _vp, ctypes.POINTER(Stats)]),
@@ -241,6 +242,16 @@ class MDP:
         v = _dev_tensor(V, torch.float32, self.num_states, "V")
         _check(load().vi_solve(self._h, v, float(tol), int(max_iter), _stream_ptr(stream),
                                ctypes.byref(st)), st)
+        return st.as_dict()
+
+    def vi_solve_noalloc(self, V, tol: float = 1e-6, max_iter: int = 1_000_000, stream=None) -> dict:
+        """vi_solve with all device scratch in the library's static array
+        (vi_solve_noalloc: no device allocation; instances up to its 64 MiB)."""
+        import torch
+        st = Stats()
+        v = _dev_tensor(V, torch.float32, self.num_states, "V")
+        _check(load().vi_solve_noalloc(self._h, v, float(tol), int(max_iter), _stream_ptr(stream),
+                                       ctypes.byref(st)), st)
         return st.as_dict()
 
     def vi_solve_bsdi(self, V, tol: float = 1e-6, inner: int = 4, max_iter: int = 1_000_000,

@@ -793,6 +793,164 @@ int vi_solve(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, void* hip_st
                          false, mdpvi::vi_sweep_grid(M, form));
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free value iteration
+//
+// vi_solve_noalloc runs the sweeps of vi_solve with every piece of device
+// scratch (control words, residual words, the two FP64 arrival-term arrays,
+// the ping-pong value buffer) carved out of one file-scope device array.
+// Each device that runs it holds its own copy of the array until the process
+// ends; the host reaches a device's copy only through the address
+// hipGetSymbolAddress returns with that device current (the array's name in
+// host code is a host-side stand-in, not a device address).
+
+namespace {
+constexpr size_t kNoAllocBytes = size_t{64} << 20;
+constexpr int kNoAllocDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kNoAllocDevices] = {};
+
+// The current device's copy of the scratch array (looked up once per device).
+int noalloc_scratch(unsigned char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocDevices)
+    return fail(MDPVI_EINVAL, "device %d is beyond the %d the allocation-free form supports", dev,
+                kNoAllocDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(MDPVI_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return MDPVI_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+extern "C" {
+
+int vi_solve_noalloc(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, void* hip_stream,
+                     mdpvi_stats* st) {
+  if (!h || !V) return fail(MDPVI_EINVAL, "NULL handle or value array");
+  if (!(tol > 0)) return fail(MDPVI_EINVAL, "tol=%g must be > 0", tol);
+  if (max_iter < 1) return fail(MDPVI_EINVAL, "max_iter=%lld must be >= 1", (long long)max_iter);
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const Model& M = h->M;
+  // the form of vi_solve without the tuning cache: the handle's explicit
+  // choice, else the tile form where worthwhile, else the direct forms; the
+  // tiles run in index order (every order gives the same iterates)
+  mdpvi::TileShape S{};
+  const int fallback = mdpvi::exact_shape(M) ? 0 : mdpvi::slab_digits(M);
+  int form = h->slab_t;
+  if (form < 0)
+    form = mdpvi::vi_tile_shape(M, &S) && mdpvi::tile_worthwhile(S) ? MDPVI_FORM_TILE + auto_walkers(S, kTileWalkersVi)
+                                                                  : fallback;
+  if (is_tile_form(form)) {
+    if (!mdpvi::vi_tile_shape(M, &S)) {
+      form = fallback;
+    } else {
+      mdpvi::tile_set_walkers(&S, form - MDPVI_FORM_TILE, cu_count());
+      S.order = nullptr;
+    }
+  }
+  const bool tile = is_tile_form(form);
+  const bool arrival = tile || (form == 0 && mdpvi::exact_shape(M));
+  const uint32_t grid = tile ? S.grid : mdpvi::vi_sweep_grid(M, form);
+  // scratch layout: control words | residual words | A0 | A1 | second values
+  const size_t a_doubles = static_cast<size_t>(M.n_occ) + mdpvi::kSentinel;
+  const size_t o_res = round256(sizeof(Ctl));
+  const size_t o_a0 = o_res + round256(mdpvi::res_doubles(grid) * sizeof(double));
+  const size_t o_a1 = o_a0 + (arrival ? round256(a_doubles * sizeof(double)) : 0);
+  const size_t o_v = o_a1 + (arrival ? round256(a_doubles * sizeof(double)) : 0);
+  const size_t need = o_v + round256(static_cast<size_t>(M.n_states) * sizeof(float));
+  if (need > kNoAllocBytes)
+    return fail(MDPVI_ERANGE,
+                "%lld states need %zu bytes of scratch; the allocation-free form holds %zu (use vi_solve)",
+                (long long)M.n_states, need, kNoAllocBytes);
+  unsigned char* base = nullptr;
+  int rc = noalloc_scratch(&base);
+  if (rc) return rc;
+  Ctl* ctl = reinterpret_cast<Ctl*>(base);
+  double* res = reinterpret_cast<double*>(base + o_res);
+  double* A[2] = {arrival ? reinterpret_cast<double*>(base + o_a0) : nullptr,
+                  arrival ? reinterpret_cast<double*>(base + o_a1) : nullptr};
+  float* buf[2] = {V, reinterpret_cast<float*>(base + o_v)};
+
+  // control and residual words start cleared (a kernel, not a memset)
+  HIP_TRY(mdpvi::launch_ctl_init(ctl, res, s));
+  if (arrival) HIP_TRY(mdpvi::launch_arrival_init(M, V, A[0], A[1], s));
+  int64_t issued = 0, chunk = 8;
+  long long done = -1;
+  while (issued < max_iter) {
+    const int64_t n = std::min<int64_t>(chunk, max_iter - issued);
+    for (int64_t i = 0; i < n; ++i) {
+      const long long j = static_cast<long long>(issued + i);
+      if (tile)
+        HIP_TRY(mdpvi::launch_vi_tile(M, S, buf[j & 1], buf[(j + 1) & 1], A[j & 1], A[(j + 1) & 1], ctl, res, j,
+                                      tol, s));
+      else
+        HIP_TRY(mdpvi::launch_vi_sweep(M, buf[j & 1], buf[(j + 1) & 1], ctl, res, j, tol, s, form,
+                                       arrival ? A : nullptr));
+    }
+    HIP_TRY(hipMemcpyAsync(&done, &ctl->done_iter, sizeof done, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    issued += n;
+    if (done >= 0) break;
+    if (chunk < kMaxChunk) chunk *= 2;
+  }
+  const int64_t final_iter = done >= 0 ? done : issued;
+  // largest workgroup residual of the last sweep, read in pieces
+  double r = 0.0;
+  {
+    const double* words = res + static_cast<size_t>((final_iter - 1) % mdpvi::kResSlots) * grid;
+    double part[512];
+    for (uint32_t b0 = 0; b0 < grid && !std::isnan(r); b0 += 512) {
+      const uint32_t m = std::min<uint32_t>(512, grid - b0);
+      HIP_TRY(hipMemcpyAsync(part, words + b0, m * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      for (uint32_t b = 0; b < m; ++b) {
+        if (std::isnan(part[b])) {
+          r = part[b];
+          break;
+        }
+        r = std::max(r, part[b]);
+      }
+    }
+  }
+  if (final_iter & 1)
+    HIP_TRY(hipMemcpyAsync(V, buf[1], static_cast<size_t>(M.n_states) * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (st) {
+    st->iterations = final_iter;
+    st->residual_inf = r;
+    st->bound_inf = M.gamma / (1.0 - M.gamma) * r;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    st->backups = static_cast<double>(h->feasible_pairs) * static_cast<double>(final_iter);
+    st->bytes = 8.0 * static_cast<double>(M.n_states) * static_cast<double>(final_iter);
+    st->sweep_seconds = 0.0;
+  }
+  if (std::isnan(r) || std::isinf(r))
+    return fail(MDPVI_ENAN, "non-finite residual after %lld sweeps", (long long)final_iter);
+  if (!(r < tol))
+    return fail(MDPVI_ENOCONV, "residual %.3e >= tol %.3e after %lld sweeps (max_iter)", r, tol,
+                (long long)final_iter);
+  return MDPVI_OK;
+}
+
 int vi_solve_bsdi(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, int32_t inner, void* hip_stream,
                   mdpvi_stats* st) {
   if (!h || !V) return fail(MDPVI_EINVAL, "NULL handle or value array");
