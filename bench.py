@@ -54,6 +54,15 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def vi_kernel_name(form: int) -> str:
+    """The value-iteration sweep kernel a form code runs."""
+    if form >= 32:
+        return "vi_row_kernel"
+    if form >= 16:
+        return "vi_tile_kernel"
+    return "vi_slab_kernel" if form > 0 else "vi_exact_kernel"
+
+
 def batched_vs_per_instance(mdpvi, n: int, tol: float) -> dict:
     """The 512-instance parameter sweep solved by one vi_solve_batch call and
     by one vi_solve call per instance on the same stream (handles built and
@@ -87,6 +96,63 @@ def batched_vs_per_instance(mdpvi, n: int, tol: float) -> dict:
             "batched_seconds": t_batch, "batched_backups_per_s": st["backups"] / t_batch,
             "per_instance_seconds": t_single, "per_instance_backups_per_s": backups_single / t_single,
             "speedup": t_single / t_batch, "max_sweeps": max(its)}
+
+
+def tolerance_runs(mdp, V, tol: float, t_abs: float, sweeps_abs) -> dict:
+    """The stopping test ||dV||_inf < 1e-6 with FP32 values: at ||V||_inf
+    above 16 the FP32 spacing exceeds 1e-6, so the absolute test passes only
+    at an exact FP32 fixed point.  Reported side by side, each with its
+    label: the timed absolute test; the relative test ||dV||_inf <= 1e-6
+    ||V||_inf; and the exact FP32 fixed point (residual 0)."""
+    import numpy as np
+    import torch
+    vmax = float(V.abs().max())
+    spacing = float(np.spacing(np.float32(vmax)))
+    out = {"V_inf": vmax, "fp32_spacing_at_V_inf": spacing,
+           "abs": {"label": f"||dV||_inf < {tol:g} (FP32 spacing at ||V||_inf is {spacing:.2g}: "
+                            + ("an exact FP32 fixed point" if spacing > tol else "a true tolerance") + ")",
+                   "seconds": t_abs, "sweeps": sweeps_abs}}
+    W = torch.zeros_like(V)
+    st = mdp.vi_solve(W, tol=tol * vmax)
+    out["rel"] = {"label": f"||dV||_inf < {tol:g} * ||V||_inf = {tol * vmax:.3g}",
+                  "seconds": st["seconds"], "sweeps": st["iterations"]}
+    W.zero_()
+    st = mdp.vi_solve(W, tol=1e-300)
+    out["fixed_point"] = {"label": "||dV||_inf = 0: the exact FP32 fixed point",
+                          "seconds": st["seconds"], "sweeps": st["iterations"],
+                          "equals_abs_result": bool(torch.equal(W, V))}
+    return out
+
+
+def supplementary_k7(mdpvi, tol: float) -> dict:
+    """Value iteration on the instance beyond the last-level cache (K=7, C=10,
+    J=3: 58,461,513 states, 468 MB of FP32 values read and written per sweep):
+    its time to tolerance and the sweep kernel's achieved bandwidth."""
+    import torch
+    inst, desc = workload("large_single_k7")
+    mdp = mdpvi.MDP.from_instance(inst)
+    vi_form, _ = mdp.sweep_forms()
+    V = torch.zeros(mdp.num_states, dtype=torch.float32, device="cuda")
+    try:
+        mdp.vi_solve(V, tol=tol, max_iter=8)   # first-use allocations, tile order
+    except mdpvi.MdpviError:
+        pass
+    V.zero_()
+    st = mdp.vi_solve(V, tol=tol)
+    N = mdp.num_states
+    avg = st["seconds"] / st["iterations"]
+    ach = VI_BYTES_PER_STATE * N / avg / 1e9
+    impl = vi_kernel_name(vi_form)
+    srcs = {"vi_row_kernel": ["paper_2012_12419_amd/csrc/row_vi.hip", "paper_2012_12419_amd/csrc/row.hpp",
+                              "paper_2012_12419_amd/csrc/tile.hpp"],
+            "vi_tile_kernel": ["paper_2012_12419_amd/csrc/tile_vi.hip", "paper_2012_12419_amd/csrc/tile.hpp"]}
+    return {"workload": f"large_single_k7: {desc}", "states": N, "form": vi_form, "kernel": impl,
+            "sweeps": st["iterations"], "seconds": st["seconds"],
+            "backups_per_s": st["backups"] / st["seconds"], "avg_us": avg * 1e6,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS,
+                         "traffic": traffic_record(srcs[impl], f"{impl}_large_single_k7")
+                         if impl in srcs else None}}
 
 
 def bsdi_comparison(mdp, N: int, tol: float, inners=(1, 2, 4, 8)) -> dict:
@@ -187,6 +253,10 @@ def gradient_workloads(mdpvi, n_batch: int, tol: float) -> dict:
         torch.cuda.synchronize()
         return time.perf_counter() - t0, g, Jv, st
 
+    inst = W.gradient_instance()
+    tuner = mdpvi.MDP.from_instance(inst)
+    tuner.autotune(trials=5)          # untimed: records the forms for this shape
+    adj_form = tuner.adjoint_form()
     single()   # first-use allocations
     t_single, g, Jv, st_adj = single()
 
@@ -228,6 +298,8 @@ def gradient_workloads(mdpvi, n_batch: int, tol: float) -> dict:
     return {"single": {"workload": "gradient: K=5 C=10 J=2 sizes(1,2), gamma 0.98: 322,102 states",
                        "seconds": t_single, "gradients_per_s": 1.0 / t_single, "J": Jv,
                        "adjoint_sweeps": st_adj["iterations"], "adjoint_seconds": st_adj["seconds"],
+                       "adjoint_us_per_sweep": st_adj["seconds"] / st_adj["iterations"] * 1e6,
+                       "adjoint_form": adj_form,
                        "dJ_dtheta": list(g)},
             "batched": {"instances": n_batch, "states": N, "seconds": t_batch,
                         "gradients_per_s": n_batch / t_batch,
@@ -253,9 +325,22 @@ def traffic_record(kernel_files, name: str):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(inst, sweeps: int) -> dict:
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(inst, sweeps: int, gpu_sweeps, gpu_seconds) -> dict:
     """The FP64 NumPy oracle's Jacobi sweep, single-threaded, on `sweeps`
-    sweeps from V = 0 of the same instance."""
+    sweeps from V = 0 of the same instance; its time to the GPU's stopping
+    sweep is extrapolated from the per-sweep time."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -268,9 +353,16 @@ def cpu_baseline(inst, sweeps: int) -> dict:
         for _ in range(sweeps):
             V = vi.bellman(inst, V, g)
         dt = time.perf_counter() - t0
-    return {"value": pairs * sweeps / dt, "unit": "backups/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sweeps} FP64 Jacobi sweeps from V=0 of the same instance "
-                      f"({pairs} feasible pairs each, {dt:.1f} s), NumPy on one host thread"}
+    out = {"value": pairs * sweeps / dt, "unit": "backups/s", "cores": 1, "kind": "oracle",
+           "sample": f"{sweeps} FP64 Jacobi sweeps from V=0 of the same instance "
+                     f"({pairs} feasible pairs each, {dt:.1f} s), NumPy on one host thread",
+           "cpu_model": _cpu_model(), "host_cores_available": len(os.sched_getaffinity(0)),
+           "seconds_per_sweep": dt / sweeps}
+    if gpu_sweeps:
+        out["time_to_tol_extrapolated_s"] = dt / sweeps * gpu_sweeps
+        out["time_to_tol_note"] = (f"per-sweep time x the {gpu_sweeps} sweeps the GPU ran to the same "
+                                   f"stopping test (extrapolated; GPU: {gpu_seconds:.4f} s)")
+    return out
 
 
 def main() -> int:
@@ -296,6 +388,10 @@ def main() -> int:
                     help="instances of the batched gradient pipeline (0: skip the gradient fields)")
     ap.add_argument("--static", type=int, default=1_000_000,
                     help="random static scenarios for the first-fit placement timing (0: skip)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="time the automatic forms without running the autotuner first")
+    ap.add_argument("--no-k7", dest="k7", action="store_false",
+                    help="skip the supplementary instance beyond the last-level cache (K=7)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -318,7 +414,15 @@ def main() -> int:
     inst, desc = workload(args.workload)
     mdp = mdpvi.MDP.from_instance(inst)
     mdp.set_sweep_form(args.sweep_form)
+    tuned = None
+    if args.autotune and args.sweep_form == -1:
+        # untimed: the autotuner records the fastest form of each sweep for
+        # this shape, and the automatic choice of the timed steps takes it
+        tf, tus = mdp.autotune(trials=5)
+        tuned = {"vi_form": tf, "vi_us_per_sweep": tus}
     vi_form, ev_form = mdp.sweep_forms()
+    if tuned is not None:
+        tuned.update({"eval_form": ev_form, "adjoint_form": mdp.adjoint_form()})
     N = mdp.num_states
     dev = "cuda:0"
     V = torch.zeros(N, dtype=torch.float32, device=dev)
@@ -354,6 +458,8 @@ def main() -> int:
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
+    t_tol = sum(r[0]["seconds"] for r in recs) / len(recs)
+    tol_labels = tolerance_runs(mdp, V, args.tol, t_tol, recs[0][0]["iterations"] if recs else None)
     pi_run = policy_iteration_run(mdp, args.eval_tol)
     bsdi = None
     if args.bsdi:
@@ -383,16 +489,15 @@ def main() -> int:
     vi_sweeps = [r[0]["iterations"] for r in recs]
     ev_sweeps = [r[1]["iterations"] for r in recs]
     g_sweeps = [r[2]["iterations"] for r in recs]
-    t_tol = sum(r[0]["seconds"] for r in recs) / len(recs)
 
     roof = None
     kernels = {}
     if recs:
-        tile = 16
-        vi_impl = ("vi_tile_kernel" if vi_form >= tile else
-                   "vi_slab_kernel" if vi_form > 0 else "vi_exact_kernel")
-        ev_impl = "eval_tile_kernel" if ev_form >= tile else "eval_exact_kernel"
+        vi_impl = vi_kernel_name(vi_form)
+        ev_impl = "eval_tile_kernel" if ev_form >= mdpvi.FORM_TILE else "eval_exact_kernel"
         srcs = {"vi_tile_kernel": ["paper_2012_12419_amd/csrc/tile_vi.hip", "paper_2012_12419_amd/csrc/tile.hpp"],
+                "vi_row_kernel": ["paper_2012_12419_amd/csrc/row_vi.hip", "paper_2012_12419_amd/csrc/row.hpp",
+                                  "paper_2012_12419_amd/csrc/tile.hpp"],
                 "vi_exact_kernel": ["paper_2012_12419_amd/csrc/sweep.hip",
                                     "paper_2012_12419_amd/csrc/sweep_impl.hpp"],
                 "vi_slab_kernel": ["paper_2012_12419_amd/csrc/sweep.hip",
@@ -444,14 +549,20 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "fp32-storage/fp64-sum",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "states": N,
                    "feasible_pairs_per_sweep": mdp.feasible_pairs, "tol": args.tol,
                    "eval_tol": args.eval_tol, "sweep_form": args.sweep_form,
                    "forms_in_use": {"vi": vi_form, "eval": ev_form},
-                   "values": "FP32 storage, FP64 sums (VI); FP64 (evaluation)"},
+                   "autotuned": tuned,
+                   "values": "FP32 storage, FP64 sums (VI); FP64 (evaluation)",
+                   "value_composition": "per step: value iteration's feasible (state, action) backups "
+                                        "over its sweeps, plus one (state, policy action) backup per "
+                                        "state per FP64 evaluation sweep of pi* and of the least-loaded "
+                                        "heuristic; divided by the steps' wall time"},
         "time_to_tol_s": t_tol,
+        "time_to_tol": tol_labels,
         "vi_sweeps": vi_sweeps,
         "eval_sweeps": ev_sweeps,
         "greedy_eval_sweeps": g_sweeps,
@@ -471,8 +582,11 @@ def main() -> int:
         out["gradient"] = gradient_workloads(mdpvi, args.grad_batch, args.tol)
     if args.static:
         out["static_bot"] = static_bot_run(mdpvi, args.static)
+    if args.k7:
+        out["supplementary_beyond_cache"] = supplementary_k7(mdpvi, args.tol)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps, vi_sweeps[0] if vi_sweeps else None,
+                                           t_tol)
     print(json.dumps(out), flush=True)
     return 0
 

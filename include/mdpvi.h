@@ -60,6 +60,7 @@ extern "C" {
 #define MDPVI_MAX_K 16       /* hosts */
 #define MDPVI_MAX_J 8        /* task classes */
 #define MDPVI_FORM_TILE 16   /* mdp_set_sweep_form: the tile form */
+#define MDPVI_FORM_ROW 32    /* mdp_set_sweep_form: the row form of the tile sweep */
 
 /* Model parameters (Sec. V-B..V-E).  All pointers are host pointers to J
  * entries, read during mdp_build only.
@@ -303,10 +304,15 @@ int vi_solve_bsdi(mdpvi_mdp_t h, float *V, double tol, int64_t max_iter, int32_t
  * environment variable MDPVI_TILE_ORDER (read at every solve; a measurement
  * aid) forces "index" (contiguous eighths), "rcb" or "dealN" (runs of N).
  * Every order and every w give bit-identical iterates.
- * Automatic mode uses the tile form where it applies, unless mdp_autotune
- * recorded another form for the shape, then the exact-shape direct form,
- * then the slab form.  Errors: MDPVI_EINVAL (NULL handle, t >= K, a slab
- * that does not fit 64 KB of LDS, or a tile form that does not apply).     */
+ * MDPVI_FORM_ROW + w (w = 0..8): the row form of the value-iteration tile
+ * sweep (tiles of T = 3 digits, each lane a chunk of four consecutive
+ * occupancies along digit 0; compiled for K in 5..7, C = 10, J <= 3
+ * distinct sizes of at most 3 units); evaluation runs in the tile form.
+ * Automatic mode uses the form mdp_autotune recorded for the shape, else
+ * the row form where it applies and a sweep's working set exceeds 256 MB,
+ * else the tile form, else the exact-shape direct form, else the slab form.
+ * Errors: MDPVI_EINVAL (NULL handle, t >= K, a slab that does not fit 64 KB
+ * of LDS, or a tile or row form that does not apply).                       */
 int mdp_set_sweep_form(mdpvi_mdp_t h, int32_t slab_digits);
 
 /* Batched extraction / greedy heuristic: as policy_extract(_f64) and
@@ -338,21 +344,34 @@ int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t *pi, const double *V_pi, flo
 /* The forms the next vi_solve and policy_eval on this handle run (after the
  * automatic choice): vi, eval (host, nullable).  A value in 1..K-1 is a slab
  * depth, 0 the direct form (the exact-shape one where it applies),
- * MDPVI_FORM_TILE + w the tile form.  Errors: MDPVI_EINVAL (NULL handle).   */
+ * MDPVI_FORM_TILE + w the tile form, MDPVI_FORM_ROW + w the row form of
+ * value iteration.  Errors: MDPVI_EINVAL (NULL handle).                     */
 int mdp_sweep_forms(mdpvi_mdp_t h, int32_t *vi, int32_t *eval);
 
-/* Autotuner: times every applicable value-iteration form (direct, LDS slabs
- * of 1..K-1 low digits that fit 64 KB, tile) on this instance, `trials` single sweeps
- * each from V (device float[N], read only; the sweeps write the handle's
- * scratch), keeps the form with the smallest median time, and records it
- * for the shape (GPU arch, K, C, J, sizes): later vi_solve calls in automatic
- * mode on any handle of that shape use it.  When the environment variable
- * MDPVI_AUTOTUNE_CACHE names a file, the records are loaded from and saved
- * to it as JSON.  best_form / best_us (host, nullable): the chosen form and
- * its median microseconds per sweep.  Synchronous.
- * Errors: MDPVI_EINVAL, MDPVI_EDEVICE, MDPVI_ENOMEM.                        */
+/* Autotuner (a tuning step of this library; not in the paper): times, on
+ * this instance, `trials` single sweeps of every applicable form of
+ *   value iteration (direct, LDS slabs of 1..K-1 low digits that fit 64 KB,
+ *     tile and row forms with 0..4 workgroups per CU), from V;
+ *   FP64 evaluation (direct, tile with 0..5 workgroups per CU) and
+ *   the adjoint sweep (generic and exact-shape kernels, 1, 2 or 4
+ *     occupancies per thread), both on the least-loaded policy
+ * (V: device float[N], read only; the sweeps write the handle's scratch and
+ * temporary buffers), keeps each operation's form with the smallest median
+ * time and records it for the shape (GPU arch, K, C, J, sizes): later calls
+ * in automatic mode on any handle of that shape use it (vi_solve,
+ * policy_eval, vi_adjoint and the calls built on them).  When the
+ * environment variable MDPVI_AUTOTUNE_CACHE names a file, the records are
+ * loaded from and saved to it as JSON.  best_form / best_us (host,
+ * nullable): value iteration's chosen form and its median microseconds per
+ * sweep.  Synchronous.  Errors: MDPVI_EINVAL, MDPVI_EDEVICE, MDPVI_ENOMEM. */
 int mdp_autotune(mdpvi_mdp_t h, const float *V, int32_t trials, void *hip_stream,
                  int32_t *best_form, double *best_us);
+
+/* The adjoint sweep form the next vi_adjoint on this handle runs: 16 + OPT
+ * for the exact-shape kernels (K in 3..8, J <= 3), OPT for the generic ones,
+ * OPT in {1, 2, 4} occupancies per thread (the recorded tuning, else one per
+ * thread below 2^21 occupancies and four above); -1 for a NULL handle.      */
+int32_t mdp_adjoint_form(mdpvi_mdp_t h);
 
 /* Per-sweep kernel timing for the iterative calls of this handle: when on,
  * every sweep launch is bracketed by two HIP events and their elapsed times

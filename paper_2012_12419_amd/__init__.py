@@ -31,6 +31,7 @@ ENAN = -4
 EDEVICE = -5
 ENOMEM = -6
 FORM_TILE = 16   # mdp_set_sweep_form: the tile form
+FORM_ROW = 32    # mdp_set_sweep_form: the row form of the tile sweeps
 STATIC_PAID = -1    # static placement: the task went to the paid cloud
 STATIC_EMPTY = -2   # static placement: empty task slot (need 0)
 _NAMES = {EINVAL: "EINVAL", ERANGE: "ERANGE", ENOCONV: "ENOCONV", ENAN: "ENAN",
@@ -97,6 +98,7 @@ SIGNATURES = {
     "vi_solve_bsdi": (ctypes.c_int, [_vp, _vp, _c_double, _c_int64, _c_int32, _vp, ctypes.POINTER(Stats)]),
     "policy_iteration": (ctypes.c_int, [_vp, _vp, _vp, _c_double, _c_int64, _c_double, _c_int64, _vp,
                                         ctypes.POINTER(Stats), ctypes.POINTER(_c_int64)]),
+    "mdp_adjoint_form": (_c_int32, [_vp]),
     "mdp_sweep_forms": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32)]),
     "mdp_autotune": (ctypes.c_int, [_vp, _vp, _c_int32, _vp, ctypes.POINTER(_c_int32),
                                     ctypes.POINTER(_c_double)]),
@@ -223,6 +225,10 @@ class MDP:
         a, b = _c_int32(), _c_int32()
         _check(load().mdp_sweep_forms(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def adjoint_form(self) -> int:
+        """The adjoint sweep form the next vi_adjoint runs (mdp_adjoint_form)."""
+        return int(load().mdp_adjoint_form(self._h))
 
     def autotune(self, V=None, trials: int = 10, stream=None):
         """Time every sweep form on this instance; returns (best form, us per sweep)."""

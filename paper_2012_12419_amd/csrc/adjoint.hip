@@ -24,6 +24,7 @@
 #include "adjoint_impl.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
+#include "tile.hpp"
 
 #include <type_traits>
 
@@ -31,7 +32,7 @@ namespace mdpvi {
 
 // OPT occupancies per thread: 1 below kAdjointWideOcc occupancies, so that a
 // small instance still spreads over every CU; kOccPerThread above.
-template <int KMAX, int JMAX, typename Idx, int OPT>
+template <int KMAX, int JMAX, typename Idx, int OPT, bool EXACT>
 __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(Model M, const uint8_t* __restrict__ pi,
                                                                 const float* __restrict__ win,
                                                                 float* __restrict__ wout, Ctl* ctl,
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(Model M, const ui
 #pragma unroll
   for (int i = 0; i < OPT; ++i) {
     const Idx o = base + static_cast<Idx>(i * kBlock);
-    if (o < static_cast<Idx>(M.n_occ)) dsum += adjoint_occupancy<KMAX, JMAX>(M, pi, win, wout, o);
+    if (o < static_cast<Idx>(M.n_occ)) dsum += adjoint_occupancy<KMAX, JMAX, Idx, EXACT>(M, pi, win, wout, o);
   }
   block_sum_to(dsum, res, j);
 }
@@ -172,24 +173,59 @@ size_t grad_partial_doubles(const Model& M) {
   return static_cast<size_t>(sweep_blocks(M)) * (2 * (M.J <= 4 ? 4 : 8) + 2);
 }
 
-hipError_t launch_adjoint_sweep(const Model& M, const uint8_t* pi, const float* win, float* wout,
-                                Ctl* ctl, double* res, long long j, double tol, hipStream_t s) {
+// Adjoint sweep forms: kAdjointExact + OPT (exact-shape kernels, K in 3..8,
+// J <= 3, OPT occupancies per thread) or OPT alone (the generic kernels);
+// 0 picks the exact form where it applies, with one occupancy per thread
+// below kAdjointWideOcc occupancies and kOccPerThread above.
+bool adjoint_exact_shape(const Model& M) {
+  return M.K >= 3 && M.K <= 8 && M.J >= 1 && M.J <= 3 && use_32bit_index(M);
+}
+
+int adjoint_auto_form(const Model& M) {
+  const int opt = M.n_occ < kAdjointWideOcc ? 1 : kOccPerThread;
+  return adjoint_exact_shape(M) ? kAdjointExact + opt : opt;
+}
+
+bool adjoint_form_valid(const Model& M, int form) {
+  const int opt = form & (kAdjointExact - 1);
+  if (opt != 1 && opt != 2 && opt != 4) return false;
+  return (form & kAdjointExact) ? adjoint_exact_shape(M) : (form == opt);
+}
+
+template <int OPT>
+static hipError_t launch_adjoint_opt(const Model& M, bool exact, const uint8_t* pi, const float* win,
+                                     float* wout, Ctl* ctl, double* res, long long j, double tol, hipStream_t s) {
+  const dim3 grid(adjoint_blocks(M, OPT));
+  if (exact) {
+    return tile_dispatch(M.K, M.J, 2, [&](auto kc, auto jc, auto) {
+      constexpr int Kc = decltype(kc)::value, Jc = decltype(jc)::value;
+      hipLaunchKernelGGL((adjoint_sweep_kernel<Kc, Jc, uint32_t, OPT, true>), grid, dim3(kBlock), 0, s, M, pi, win,
+                         wout, ctl, res, j, tol);
+      return hipGetLastError();
+    });
+  }
   return dispatch_kj(M, [&](auto km, auto jm) {
     constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
-    if (M.n_occ < kAdjointWideOcc) {
-      hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint32_t, 1>), dim3(adjoint_blocks(M, 1)), dim3(kBlock),
-                         0, s, M, pi, win, wout, ctl, res, j, tol);
-    } else if (use_32bit_index(M)) {
-      hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint32_t, kOccPerThread>),
-                         dim3(adjoint_blocks(M, kOccPerThread)), dim3(kBlock), 0, s, M, pi, win, wout, ctl, res,
-                         j, tol);
-    } else {
-      hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint64_t, kOccPerThread>),
-                         dim3(adjoint_blocks(M, kOccPerThread)), dim3(kBlock), 0, s, M, pi, win, wout, ctl, res,
-                         j, tol);
-    }
+    if (use_32bit_index(M))
+      hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint32_t, OPT, false>), grid, dim3(kBlock), 0, s, M, pi,
+                         win, wout, ctl, res, j, tol);
+    else
+      hipLaunchKernelGGL((adjoint_sweep_kernel<KM, JM, uint64_t, OPT, false>), grid, dim3(kBlock), 0, s, M, pi,
+                         win, wout, ctl, res, j, tol);
     return hipGetLastError();
   });
+}
+
+hipError_t launch_adjoint_sweep(const Model& M, int form, const uint8_t* pi, const float* win, float* wout,
+                                Ctl* ctl, double* res, long long j, double tol, hipStream_t s) {
+  if (form == 0) form = adjoint_auto_form(M);
+  if (!adjoint_form_valid(M, form)) return hipErrorInvalidValue;
+  const bool exact = (form & kAdjointExact) != 0;
+  switch (form & (kAdjointExact - 1)) {
+    case 1: return launch_adjoint_opt<1>(M, exact, pi, win, wout, ctl, res, j, tol, s);
+    case 2: return launch_adjoint_opt<2>(M, exact, pi, win, wout, ctl, res, j, tol, s);
+    default: return launch_adjoint_opt<4>(M, exact, pi, win, wout, ctl, res, j, tol, s);
+  }
 }
 
 hipError_t launch_grad(const Model& M, const uint8_t* pi, const double* V, const float* w,

@@ -7,7 +7,10 @@
 
 namespace mdpvi {
 
-template <int KMAX, int JMAX, typename Idx>
+// Transposed backup of every class of occupancy o (the sweep's arithmetic,
+// in this order, for every form).  EXACT: KMAX = K and JMAX = J, so the
+// host and class loops need no run-time bounds.
+template <int KMAX, int JMAX, typename Idx, bool EXACT = false>
 __device__ __forceinline__ double adjoint_occupancy(const Model& M, const uint8_t* __restrict__ pi,
                                                     const float* __restrict__ win,
                                                     float* __restrict__ wout, Idx o) {
@@ -22,18 +25,18 @@ __device__ __forceinline__ double adjoint_occupancy(const Model& M, const uint8_
   double B = 0.0;
 #pragma unroll
   for (int e = 0; e < JMAX; ++e) {
-    if (e < M.J) {
+    if (EXACT || e < M.J) {
       const Idx s = o + e * nocc;
       if (pi[s] == M.K) B += static_cast<double>(win[s]);
     }
   }
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
-    if (k < M.K) {
+    if (EXACT || k < M.K) {
       const Idx st = static_cast<Idx>(M.stride[k]);
 #pragma unroll
       for (int e = 0; e < JMAX; ++e) {
-        if (e < M.J && n[k] >= M.size[e]) {
+        if ((EXACT || e < M.J) && n[k] >= M.size[e]) {
           const Idx src = o - static_cast<Idx>(M.size[e]) * st + e * nocc;
           if (pi[src] == k) B += static_cast<double>(win[src]);
         }
@@ -45,14 +48,14 @@ __device__ __forceinline__ double adjoint_occupancy(const Model& M, const uint8_
   double dsum = 0.0;
 #pragma unroll
   for (int e = 0; e < JMAX; ++e) {
-    if (e < M.J) {
+    if (EXACT || e < M.J) {
       const Idx base = o + e * nocc;
       const float wold = win[base];
       double acc = fma(M.p[e], B, idle * static_cast<double>(wold));
       double rs = 0.0;
 #pragma unroll
       for (int k = 0; k < KMAX; ++k) {
-        if (k < M.K) {
+        if (EXACT || k < M.K) {
           const Idx st = static_cast<Idx>(M.stride[k]);
           if (n[k] < M.C) acc = fma(M.mu_L * (n[k] + 1), static_cast<double>(win[base + st]), acc);
           if (n[k] == 0) {

@@ -168,7 +168,7 @@ int ensure_aux(mdpvi_mdp* h, size_t doubles) {
   return MDPVI_OK;
 }
 
-int tune_lookup(const Model& M);
+int tune_lookup(const Model& M, const char* op);
 
 // The two FP64 arrival-term arrays (n_occ + kSentinel doubles each),
 // allocated on first use, initialised from V: A[0] = sum_e lambda_e/Lam
@@ -195,6 +195,10 @@ int cu_count() {
 }
 
 bool is_tile_form(int f) { return f >= MDPVI_FORM_TILE && f <= MDPVI_FORM_TILE + 8; }
+bool is_row_form(int f) { return f >= MDPVI_FORM_ROW && f <= MDPVI_FORM_ROW + 8; }
+// Workgroups of the column walk with w per CU: a multiple of 8.
+// The tile or row form of a form code: its walkers per CU.
+int form_walkers(int f) { return is_row_form(f) ? f - MDPVI_FORM_ROW : f - MDPVI_FORM_TILE; }
 
 // Workgroups per CU of the automatic tile form (0: one workgroup per tile).
 // With fewer tiles than two per walker, w persistent walkers per CU (4 for
@@ -203,41 +207,62 @@ bool is_tile_form(int f) { return f >= MDPVI_FORM_TILE && f <= MDPVI_FORM_TILE +
 // tile is 10-14% faster.
 constexpr int kTileWalkersVi = 4;
 constexpr int kTileWalkersEval = 5;
+// The row form's automatic choice: one persistent workgroup (384 lanes) per
+// CU; it is taken where a sweep's working set exceeds the last-level cache
+// (K = 7, C = 10: 8% faster than the tile form; within the cache the two
+// are equal to within 3%).
+constexpr int kRowWalkersVi = 1;
+constexpr double kLlcBytes = 256.0 * 1024 * 1024;
+// Bytes a sweep reads and writes once: values in and out, arrival terms in
+// and out, and for evaluation the policy.
+double vi_working_set(const Model& M) { return 8.0 * M.n_states + 16.0 * M.n_occ; }
+double eval_working_set(const Model& M) { return 17.0 * M.n_states + 16.0 * M.n_occ; }
 
 int auto_walkers(const mdpvi::TileShape& S, int w) {
   return S.n < 2u * static_cast<uint32_t>(w) * static_cast<uint32_t>(cu_count()) ? w : 0;
 }
 
 // The value-iteration form to run: the handle's choice, else the tuned one
-// for the shape, else the tile form when it applies and is worthwhile, else
-// the exact-shape direct form, else the slab form.  S is filled for the tile form.
+// for the shape, else the row form or the tile form when it applies and is
+// worthwhile, else the exact-shape direct form, else the slab form.  S is
+// filled for the tile and row forms.
 int vi_form(mdpvi_mdp* h, mdpvi::TileShape* S) {
   const Model& M = h->M;
   const int fallback = mdpvi::exact_shape(M) ? 0 : mdpvi::slab_digits(M);
   int f = h->slab_t;
   if (f < 0) {
-    const int cached = tune_lookup(M);
+    const int cached = tune_lookup(M, "vi");
     if (cached >= 0)
       f = cached;
+    else if (vi_working_set(M) > kLlcBytes && mdpvi::vi_row_shape(M, S) && mdpvi::tile_worthwhile(*S))
+      f = MDPVI_FORM_ROW + kRowWalkersVi;
     else if (mdpvi::vi_tile_shape(M, S) && mdpvi::tile_worthwhile(*S))
       f = MDPVI_FORM_TILE + auto_walkers(*S, kTileWalkersVi);
     else
       f = fallback;
   }
-  if (is_tile_form(f)) {
-    if (!mdpvi::vi_tile_shape(M, S)) return fallback;
-    mdpvi::tile_set_walkers(S, f - MDPVI_FORM_TILE, cu_count());
-  }
+  if (is_row_form(f) && !mdpvi::vi_row_shape(M, S)) f = MDPVI_FORM_TILE + form_walkers(f);
+  if (is_tile_form(f) && !mdpvi::vi_tile_shape(M, S)) return fallback;
+  if (is_tile_form(f) || is_row_form(f)) mdpvi::tile_set_walkers(S, form_walkers(f), cu_count());
   return f;
 }
 
 // The evaluation form to run: the tile form where it applies and is
-// worthwhile (or where the handle asks for it), else the direct form (0).
+// worthwhile (or where the handle asks for the tile or row form of value
+// iteration), else the direct form (0).
 int eval_form(mdpvi_mdp* h, mdpvi::TileShape* S) {
-  const bool forced = is_tile_form(h->slab_t);
+  if (h->slab_t == -1) {   // a form mdp_autotune recorded for the shape
+    const int cached = tune_lookup(h->M, "eval");
+    if (cached == 0) return 0;
+    if (is_tile_form(cached) && mdpvi::eval_tile_shape(h->M, S)) {
+      mdpvi::tile_set_walkers(S, form_walkers(cached), cu_count());
+      return cached;
+    }
+  }
+  const bool forced = is_tile_form(h->slab_t) || is_row_form(h->slab_t);
   if (!(h->slab_t == -1 || forced) || !mdpvi::eval_tile_shape(h->M, S) || !(forced || mdpvi::tile_worthwhile(*S)))
     return 0;
-  const int w = forced ? h->slab_t - MDPVI_FORM_TILE : auto_walkers(*S, kTileWalkersEval);
+  const int w = forced ? form_walkers(h->slab_t) : auto_walkers(*S, kTileWalkersEval);
   mdpvi::tile_set_walkers(S, w, cu_count());
   return MDPVI_FORM_TILE + w;
 }
@@ -245,12 +270,19 @@ int eval_form(mdpvi_mdp* h, mdpvi::TileShape* S) {
 int eval_run(mdpvi_mdp* h, const uint8_t* pi, double* V, double tol, int64_t max_iter, hipStream_t s,
              mdpvi_stats* st);
 
+// The adjoint sweep form to run: the one mdp_autotune recorded for the
+// shape, else the automatic one.
+int adjoint_form(mdpvi_mdp* h) {
+  const int cached = tune_lookup(h->M, "adjoint");
+  if (cached > 0 && mdpvi::adjoint_form_valid(h->M, cached)) return cached;
+  return mdpvi::adjoint_auto_form(h->M);
+}
+
 // Tile orders: for a sweep whose working set (values and arrival terms read
 // and written) fits the last-level cache, recursive coordinate bisection
 // (each XCD a compact block: fewest halo lines through its L2); beyond it,
 // runs of kDealRun tiles dealt round-robin (all XCDs on one region, whose
 // neighbour planes then stay in the last-level cache).
-constexpr double kLlcBytes = 256.0 * 1024 * 1024;
 constexpr uint32_t kDealRun = 16;
 
 // Points S->order at the handle's device copy of the tile order for S's tile
@@ -294,11 +326,6 @@ int set_tile_order(mdpvi_mdp* h, mdpvi::TileShape* S, double ws) {
   S->order = d;
   return MDPVI_OK;
 }
-
-// Bytes a sweep reads and writes once: values in and out, arrival terms in
-// and out, and for evaluation the policy.
-double vi_working_set(const Model& M) { return 8.0 * M.n_states + 16.0 * M.n_occ; }
-double eval_working_set(const Model& M) { return 17.0 * M.n_states + 16.0 * M.n_occ; }
 
 double bits_to_double(unsigned long long b) {
   double d;
@@ -412,14 +439,17 @@ int run_loop(mdpvi_mdp* h, T* buf0, double tol, int64_t max_iter, hipStream_t s,
 
 // ---------------------------------------------------------------- tuning cache
 //
-// Best sweep form per problem shape, kept in memory and, when the
-// environment variable MDPVI_AUTOTUNE_CACHE names a file, in that JSON file:
-//   {"gfx950|K=6|C=10|J=3|S=1,2,3": [3, 9.81], ...}   (form, microseconds per sweep)
+// Best sweep form per operation and problem shape, kept in memory and, when
+// the environment variable MDPVI_AUTOTUNE_CACHE names a file, in that JSON
+// file:
+//   {"vi|gfx950|K=6|C=10|J=3|S=1,2,3": [20, 31.2], "eval|gfx950|...": [21, 44.0],
+//    "adjoint|gfx950|...": [17, 9.1], ...}   (form, microseconds per sweep)
+// A key without an operation (an older cache file) is value iteration's.
 std::mutex g_tune_mu;
 std::map<std::string, std::pair<int, double>> g_tune;
 bool g_tune_loaded = false;
 
-std::string tune_key(const Model& M) {
+std::string tune_key(const Model& M, const char* op) {
   int dev = 0;
   hipDeviceProp_t prop;
   std::string arch = "unknown";
@@ -429,7 +459,7 @@ std::string tune_key(const Model& M) {
     if (colon != std::string::npos) arch = arch.substr(0, colon);
   }
   std::ostringstream k;
-  k << arch << "|K=" << M.K << "|C=" << M.C << "|J=" << M.J << "|S=";
+  k << op << "|" << arch << "|K=" << M.K << "|C=" << M.C << "|J=" << M.J << "|S=";
   for (int j = 0; j < M.J; ++j) k << (j ? "," : "") << M.size[j];
   return k.str();
 }
@@ -454,7 +484,8 @@ void tune_load_locked() {
     if (lb == std::string::npos || rb == std::string::npos || lb > rb) break;
     int form = 0;
     double us = 0.0;
-    if (std::sscanf(s.c_str() + lb + 1, "%d , %lf", &form, &us) == 2) g_tune[key] = {form, us};
+    if (std::sscanf(s.c_str() + lb + 1, "%d , %lf", &form, &us) == 2)
+      g_tune[key.rfind("gfx", 0) == 0 ? "vi|" + key : key] = {form, us};
     pos = rb + 1;
   }
 }
@@ -473,12 +504,20 @@ void tune_store_locked() {
   f << "}\n";
 }
 
-// Cached form for M, or -2 when none is known.
-int tune_lookup(const Model& M) {
+// Cached form of operation op ("vi", "eval", "adjoint") for M, or -2 when
+// none is known.
+int tune_lookup(const Model& M, const char* op) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();
-  auto it = g_tune.find(tune_key(M));
+  auto it = g_tune.find(tune_key(M, op));
   return it == g_tune.end() ? -2 : it->second.first;
+}
+
+void tune_record(const Model& M, const char* op, int form, double us) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tune[tune_key(M, op)] = {form, us};
+  tune_store_locked();
 }
 
 // Fill a Model from validated parameters (shared by single and batched builds).
@@ -669,6 +708,13 @@ int mdp_set_sweep_form(mdpvi_mdp_t h, int32_t slab_digits) {
     h->slab_t = slab_digits;
     return MDPVI_OK;
   }
+  if (is_row_form(slab_digits)) {
+    mdpvi::TileShape S{};
+    if (!mdpvi::vi_row_shape(h->M, &S))
+      return fail(MDPVI_EINVAL, "the row form does not apply to this instance");
+    h->slab_t = slab_digits;
+    return MDPVI_OK;
+  }
   if (slab_digits < -1 || slab_digits >= h->M.K)
     return fail(MDPVI_EINVAL, "slab_digits=%d outside [-1, K-1=%d]", slab_digits, h->M.K - 1);
   if (slab_digits > 0) {
@@ -688,7 +734,27 @@ int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream
   int rc = ensure_scratch(h, static_cast<size_t>(h->M.n_states) * sizeof(float));
   if (rc) return rc;
   const Model& M = h->M;
+  const size_t N = static_cast<size_t>(M.n_states);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // median of `trials` timed launches of one sweep (after one untimed)
+  auto time_form = [&](auto&& sweep, double* us) -> int {
+    HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));
+    HIP_TRY(sweep());
+    std::vector<float> ms(trials);
+    for (int r = 0; r < trials; ++r) {
+      HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));
+      HIP_TRY(hipEventRecord(h->ev0, s));
+      HIP_TRY(sweep());
+      HIP_TRY(hipEventRecord(h->ev1, s));
+      HIP_TRY(hipEventSynchronize(h->ev1));
+      HIP_TRY(hipEventElapsedTime(&ms[r], h->ev0, h->ev1));
+    }
+    std::sort(ms.begin(), ms.end());
+    *us = ms[trials / 2] * 1e3;
+    return MDPVI_OK;
+  };
+
+  // ---- value iteration: direct, slab, tile and row forms
   std::vector<int> forms = {0};
   if (mdpvi::use_32bit_index(M)) {
     uint64_t occ = 1;
@@ -702,55 +768,128 @@ int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream
   mdpvi::TileShape S{};
   if (mdpvi::vi_tile_shape(M, &S)) {
     for (int w = 0; w <= 4; ++w) forms.push_back(MDPVI_FORM_TILE + w);
+    mdpvi::TileShape Sr{};
+    if (mdpvi::vi_row_shape(M, &Sr))
+      for (int w = 0; w <= 4; ++w) forms.push_back(MDPVI_FORM_ROW + w);
     rc = set_tile_order(h, &S, vi_working_set(M));
     if (rc) return rc;
   }
   float* out = static_cast<float*>(h->vbuf);
   double* A[2] = {nullptr, nullptr};
-  if (mdpvi::exact_shape(M) || is_tile_form(forms.back())) {
+  if (mdpvi::exact_shape(M) || is_tile_form(forms.back()) || is_row_form(forms.back())) {
     int arc = arrival_arrays(h, V, s, A);
     if (arc) return arc;
   }
-  // sweep 0 (no stopping test) from V into the scratch buffer
-  auto sweep = [&](int form) -> hipError_t {
-    if (is_tile_form(form)) {
-      mdpvi::tile_set_walkers(&S, form - MDPVI_FORM_TILE, cu_count());
-      return mdpvi::launch_vi_tile(M, S, V, out, A[0], A[1], h->ctl, h->res, 0, 1.0, s);
-    }
-    return mdpvi::launch_vi_sweep(M, V, out, h->ctl, h->res, 0, 1.0, s, form,
-                                  (form == 0 && A[0] && mdpvi::exact_shape(M)) ? A : nullptr);
-  };
   int best = 0;
   double best_t = 1e300;
   for (int form : forms) {
-    HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));   // untimed once
-    HIP_TRY(sweep(form));
-    std::vector<float> ms(trials);
-    for (int r = 0; r < trials; ++r) {
-      HIP_TRY(mdpvi::launch_ctl_init(h->ctl, h->res, s));
-      HIP_TRY(hipEventRecord(h->ev0, s));
-      HIP_TRY(sweep(form));
-      HIP_TRY(hipEventRecord(h->ev1, s));
-      HIP_TRY(hipEventSynchronize(h->ev1));
-      HIP_TRY(hipEventElapsedTime(&ms[r], h->ev0, h->ev1));
-    }
-    std::sort(ms.begin(), ms.end());
-    const double med = ms[trials / 2] * 1e3;
-    if (med < best_t) {
-      best_t = med;
+    // sweep 0 (no stopping test) from V into the scratch buffer
+    auto sweep = [&]() -> hipError_t {
+      if (is_tile_form(form)) {
+        mdpvi::tile_set_walkers(&S, form - MDPVI_FORM_TILE, cu_count());
+        return mdpvi::launch_vi_tile(M, S, V, out, A[0], A[1], h->ctl, h->res, 0, 1.0, s);
+      }
+      if (is_row_form(form)) {
+        mdpvi::tile_set_walkers(&S, form - MDPVI_FORM_ROW, cu_count());
+        return mdpvi::launch_vi_row(M, S, V, out, A[0], A[1], h->ctl, h->res, 0, 1.0, s);
+      }
+      return mdpvi::launch_vi_sweep(M, V, out, h->ctl, h->res, 0, 1.0, s, form,
+                                    (form == 0 && A[0] && mdpvi::exact_shape(M)) ? A : nullptr);
+    };
+    double us = 0.0;
+    if ((rc = time_form(sweep, &us))) return rc;
+    if (us < best_t) {
+      best_t = us;
       best = form;
     }
   }
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    tune_load_locked();
-    g_tune[tune_key(M)] = {best, best_t};
-    tune_store_locked();
-  }
+  tune_record(M, "vi", best, best_t);
   if (best_form) *best_form = best;
   if (best_us) *best_us = best_t;
-  return MDPVI_OK;
+
+  // ---- FP64 evaluation (direct form, tile form with 0..5 workgroups per CU)
+  // and the adjoint sweep (generic and exact-shape kernels, 1, 2 or 4
+  // occupancies per thread), both on the least-loaded policy; temporary
+  // buffers only
+  uint8_t* pol = nullptr;
+  double* ev[2] = {nullptr, nullptr};
+  if (hipMalloc(reinterpret_cast<void**>(&pol), N + 16) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&ev[0]), 2 * N * sizeof(double)) != hipSuccess) {
+    if (pol) (void)hipFree(pol);
+    return fail(MDPVI_ENOMEM, "hipMalloc of the tuning buffers failed");
+  }
+  ev[1] = ev[0] + N;
+  auto release = [&]() {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(pol);
+    (void)hipFree(ev[0]);
+  };
+  auto tune_rest = [&]() -> int {
+    HIP_TRY(mdpvi::launch_greedy(M, 0, pol, s));
+    HIP_TRY(hipMemsetAsync(ev[0], 0, 2 * N * sizeof(double), s));
+    std::vector<int> eforms = {0};
+    mdpvi::TileShape Se{};
+    double* Ae[2] = {nullptr, nullptr};
+    if (mdpvi::eval_tile_shape(M, &Se)) {
+      for (int w = 0; w <= 5; ++w) eforms.push_back(MDPVI_FORM_TILE + w);
+      const size_t per = static_cast<size_t>(M.n_occ) + mdpvi::kSentinel;
+      if (!h->abuf && hipMalloc(reinterpret_cast<void**>(&h->abuf), 2 * per * sizeof(double)) != hipSuccess) {
+        h->abuf = nullptr;
+        return fail(MDPVI_ENOMEM, "hipMalloc of the arrival-term arrays failed");
+      }
+      Ae[0] = h->abuf;
+      Ae[1] = h->abuf + per;
+      int orc = set_tile_order(h, &Se, eval_working_set(M));
+      if (orc) return orc;
+      HIP_TRY(mdpvi::launch_eval_arrival_init(M, ev[0], Ae[0], s));
+    }
+    int ebest = 0;
+    double ebest_t = 1e300;
+    for (int form : eforms) {
+      auto sweep = [&]() -> hipError_t {
+        if (is_tile_form(form)) {
+          mdpvi::tile_set_walkers(&Se, form - MDPVI_FORM_TILE, cu_count());
+          return mdpvi::launch_eval_tile(M, Se, pol, ev[0], ev[1], Ae[0], Ae[1], h->ctl, h->res, 0, 1.0, s);
+        }
+        return mdpvi::launch_eval_sweep(M, pol, ev[0], ev[1], h->ctl, h->res, 0, 1.0, s);
+      };
+      double us = 0.0;
+      int trc = time_form(sweep, &us);
+      if (trc) return trc;
+      if (us < ebest_t) {
+        ebest_t = us;
+        ebest = form;
+      }
+    }
+    tune_record(M, "eval", ebest, ebest_t);
+    std::vector<int> aforms;
+    for (int opt : {1, 2, 4}) {
+      if (mdpvi::adjoint_form_valid(M, opt)) aforms.push_back(opt);
+      if (mdpvi::adjoint_form_valid(M, mdpvi::kAdjointExact + opt)) aforms.push_back(mdpvi::kAdjointExact + opt);
+    }
+    int abest = mdpvi::adjoint_auto_form(M);
+    double abest_t = 1e300;
+    for (int form : aforms) {
+      auto sweep = [&]() -> hipError_t {
+        return mdpvi::launch_adjoint_sweep(M, form, pol, V, out, h->ctl, h->res, 0, 1.0, s);
+      };
+      double us = 0.0;
+      int trc = time_form(sweep, &us);
+      if (trc) return trc;
+      if (us < abest_t) {
+        abest_t = us;
+        abest = form;
+      }
+    }
+    tune_record(M, "adjoint", abest, abest_t);
+    return MDPVI_OK;
+  };
+  rc = tune_rest();
+  release();
+  return rc;
 }
+
+int32_t mdp_adjoint_form(mdpvi_mdp_t h) { return h ? adjoint_form(h) : -1; }
 
 int64_t mdp_num_states(mdpvi_mdp_t h) { return h ? h->M.n_states : -1; }
 int32_t mdp_num_actions(mdpvi_mdp_t h) { return h ? h->M.K + 1 : -1; }
@@ -767,15 +906,24 @@ int vi_solve(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, void* hip_st
   const Model& M = h->M;
   mdpvi::TileShape S{};
   const int form = vi_form(h, &S);
+  const bool tiled = is_tile_form(form) || is_row_form(form);
   double* A[2] = {nullptr, nullptr};
-  if ((form == 0 && mdpvi::exact_shape(M)) || is_tile_form(form)) {
+  if ((form == 0 && mdpvi::exact_shape(M)) || tiled) {
     int arc = arrival_arrays(h, V, s, A);
     if (arc) return arc;
   }
-  if (is_tile_form(form)) {
+  if (tiled) {
     int orc = set_tile_order(h, &S, vi_working_set(M));
     if (orc) return orc;
   }
+  if (is_row_form(form))
+    return run_loop<float>(h, V, tol, max_iter, s, st, 8.0 * M.n_states,
+                           static_cast<double>(h->feasible_pairs),
+                           [&](long long j, float* in, float* out) {
+                             return mdpvi::launch_vi_row(M, S, in, out, A[j & 1], A[(j + 1) & 1], h->ctl, h->res,
+                                                         j, tol, s);
+                           },
+                           false, S.grid);
   if (is_tile_form(form))
     return run_loop<float>(h, V, tol, max_iter, s, st, 8.0 * M.n_states,
                            static_cast<double>(h->feasible_pairs),
@@ -856,18 +1004,22 @@ int vi_solve_noalloc(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, void
   mdpvi::TileShape S{};
   const int fallback = mdpvi::exact_shape(M) ? 0 : mdpvi::slab_digits(M);
   int form = h->slab_t;
-  if (form < 0)
-    form = mdpvi::vi_tile_shape(M, &S) && mdpvi::tile_worthwhile(S) ? MDPVI_FORM_TILE + auto_walkers(S, kTileWalkersVi)
-                                                                  : fallback;
-  if (is_tile_form(form)) {
-    if (!mdpvi::vi_tile_shape(M, &S)) {
+  if (form < 0) {
+    if (vi_working_set(M) > kLlcBytes && mdpvi::vi_row_shape(M, &S) && mdpvi::tile_worthwhile(S))
+      form = MDPVI_FORM_ROW + kRowWalkersVi;
+    else if (mdpvi::vi_tile_shape(M, &S) && mdpvi::tile_worthwhile(S))
+      form = MDPVI_FORM_TILE + auto_walkers(S, kTileWalkersVi);
+    else
       form = fallback;
-    } else {
-      mdpvi::tile_set_walkers(&S, form - MDPVI_FORM_TILE, cu_count());
-      S.order = nullptr;
-    }
   }
-  const bool tile = is_tile_form(form);
+  if (is_row_form(form) && !mdpvi::vi_row_shape(M, &S)) form = MDPVI_FORM_TILE + form_walkers(form);
+  if (is_tile_form(form) && !mdpvi::vi_tile_shape(M, &S)) form = fallback;
+  const bool row = is_row_form(form);
+  if (is_tile_form(form) || row) {
+    mdpvi::tile_set_walkers(&S, form_walkers(form), cu_count());
+    S.order = nullptr;
+  }
+  const bool tile = is_tile_form(form) || row;
   const bool arrival = tile || (form == 0 && mdpvi::exact_shape(M));
   const uint32_t grid = tile ? S.grid : mdpvi::vi_sweep_grid(M, form);
   // scratch layout: control words | residual words | A0 | A1 | second values
@@ -899,7 +1051,10 @@ int vi_solve_noalloc(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, void
     const int64_t n = std::min<int64_t>(chunk, max_iter - issued);
     for (int64_t i = 0; i < n; ++i) {
       const long long j = static_cast<long long>(issued + i);
-      if (tile)
+      if (row)
+        HIP_TRY(mdpvi::launch_vi_row(M, S, buf[j & 1], buf[(j + 1) & 1], A[j & 1], A[(j + 1) & 1], ctl, res, j,
+                                     tol, s));
+      else if (tile)
         HIP_TRY(mdpvi::launch_vi_tile(M, S, buf[j & 1], buf[(j + 1) & 1], A[j & 1], A[(j + 1) & 1], ctl, res, j,
                                       tol, s));
       else
@@ -1133,10 +1288,11 @@ int vi_adjoint(mdpvi_mdp_t h, const uint8_t* pi, const double* V_pi, float* w, d
   HIP_TRY(hipStreamSynchronize(s));
   if (h->ctl_host->flag)
     return fail(MDPVI_EINVAL, "policy has an action that is not feasible in its state");
+  const int aform = adjoint_form(h);
   rc = run_loop<float>(
       h, w, tol, max_iter, s, st, 9.0 * M.n_states, static_cast<double>(M.n_states),
       [&](long long j, float* in, float* out) {
-        return mdpvi::launch_adjoint_sweep(M, pi, in, out, h->ctl, h->res, j, tol, s);
+        return mdpvi::launch_adjoint_sweep(M, aform, pi, in, out, h->ctl, h->res, j, tol, s);
       },
       /*sum_residual=*/true, mdpvi::occ_sweep_grid(M));
   if (rc != MDPVI_OK && rc != MDPVI_ENOCONV) return rc;

@@ -51,6 +51,12 @@ bool vi_bsdi_shape(const Model& M, TileShape* S);
 hipError_t launch_vi_bsdi(const Model& M, const TileShape& S, int inner, const float* Vin, float* Vout,
                           const double* Ain, double* Aout, Ctl* ctl, double* res, long long j, double tol,
                           hipStream_t s);
+// Row form of the value-iteration tile sweep (row_vi.hip): the tiles of T = 3,
+// four consecutive occupancies along digit 0 per lane; same arrival-term
+// arrays as the tile form.
+bool vi_row_shape(const Model& M, TileShape* S);
+hipError_t launch_vi_row(const Model& M, const TileShape& S, const float* Vin, float* Vout, const double* Ain,
+                         double* Aout, Ctl* ctl, double* res, long long j, double tol, hipStream_t s);
 bool eval_tile_shape(const Model& M, TileShape* S);
 hipError_t launch_eval_arrival_init(const Model& M, const double* V, double* A, hipStream_t s);
 hipError_t launch_eval_tile(const Model& M, const TileShape& S, const uint8_t* pi, const double* Vin,
@@ -83,8 +89,14 @@ uint32_t eval_sweep_grid(const Model& M);
 // Greedy heuristic policies (0 least-loaded, 1 first-fit).
 hipError_t launch_greedy(const Model& M, int kind, uint8_t* pi, hipStream_t s);
 
-// One transposed (adjoint) sweep w^{j+1} = c + gamma P_pi^T w^j, 1-norm residual.
-hipError_t launch_adjoint_sweep(const Model& M, const uint8_t* pi, const float* win, float* wout,
+// One transposed (adjoint) sweep w^{j+1} = c + gamma P_pi^T w^j, 1-norm
+// residual.  form: kAdjointExact + OPT (exact-shape kernels) or OPT (generic
+// kernels), OPT in {1, 2, 4} occupancies per thread; 0 automatic.
+constexpr int kAdjointExact = 16;
+bool adjoint_exact_shape(const Model& M);
+int adjoint_auto_form(const Model& M);
+bool adjoint_form_valid(const Model& M, int form);
+hipError_t launch_adjoint_sweep(const Model& M, int form, const uint8_t* pi, const float* win, float* wout,
                                 Ctl* ctl, double* res, long long j, double tol, hipStream_t s);
 
 // Doubles of workgroup partials needed by launch_grad.

@@ -24,39 +24,6 @@
 
 namespace mdpvi {
 
-// Workgroup-uniform data of one tile: its first occupancy, its high digits
-// and the byte offsets (relative to the tile base, in the scalar operand of a
-// buffer load) of its high-digit neighbours.
-template <int K, int J, int T>
-struct TileHigh {
-  uint32_t o0;
-  int nh[K - T];
-  int load_high;
-  uint32_t hd4[K - T];      // release neighbour (the tile itself when n_k = 0: weight 0)
-  uint32_t hr4[K - T];      // reset neighbour
-  uint32_t ha8[K - T][J];   // placement, or the -inf sentinel block
-};
-
-template <int K, int J, int T>
-__device__ __forceinline__ void tile_high_setup(const Model& M, uint32_t tb, TileHigh<K, J, T>& H) {
-  constexpr int NH = K - T;
-  const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
-  H.o0 = tile_high<K, T>(M, tb, H.nh);
-  H.load_high = 0;
-#pragma unroll
-  for (int h = 0; h < NH; ++h) {
-    const uint32_t st = static_cast<uint32_t>(M.stride[T + h]);
-    H.hd4[h] = (H.nh[h] > 0 ? H.o0 - st : H.o0) * 4u;
-    H.hr4[h] = (H.o0 - static_cast<uint32_t>(H.nh[h]) * st) * 4u;
-#pragma unroll
-    for (int e = 0; e < J; ++e) {
-      const int s = M.size[e];
-      H.ha8[h][e] = H.nh[h] + s <= M.C ? (H.o0 + static_cast<uint32_t>(s) * st) * 8u : nocc * 8u;
-    }
-    H.load_high += H.nh[h];
-  }
-}
-
 // Backup of tile occupancy i: own values, low-digit neighbours and in-tile
 // arrival terms from the LDS image (Vl [J][occ], Al [occ + 1] with -inf at
 // occ), high-digit neighbours from global memory.  With SelfLatest the reset

@@ -106,9 +106,9 @@ def test_python_binding_refuses_cpu_tensors():
 
 @pytest.mark.parametrize("K,C,J", [(8, 10, 3), (6, 24, 3), (7, 10, 3), (6, 10, 3)])
 def test_tile_form_only_below_2gib_values(K, C, J):
-    """The tile kernels address the FP32 values through 32-bit buffer offsets,
-    so the automatic choice (and an explicit request) must not take the tile
-    form once J (C+1)^K reaches 2^29 states.  Host-only: mdp_build and the
+    """The tile and row kernels address the FP32 values through 32-bit
+    buffer offsets, so the automatic choice (and an explicit request) must
+    not take them once J (C+1)^K reaches 2^29 states.  Host-only: mdp_build and the
     form query launch nothing."""
     rc, h = _build(K=K, C=C, size=list(range(1, J + 1)), lam=[0.5] * J, reward=[1.0] * J)
     assert rc == mdpvi.OK
@@ -118,10 +118,12 @@ def test_tile_form_only_below_2gib_values(K, C, J):
         assert n == J * (C + 1) ** K
         vi_f, ev_f = ctypes.c_int32(), ctypes.c_int32()
         assert lib.mdp_sweep_forms(h, ctypes.byref(vi_f), ctypes.byref(ev_f)) == mdpvi.OK
-        is_tile = lambda f: mdpvi.FORM_TILE <= f <= mdpvi.FORM_TILE + 8
+        def is_tile(f):   # the tile, row and walk forms (32-bit buffer offsets)
+            return any(b <= f <= b + 8 for b in (mdpvi.FORM_TILE, mdpvi.FORM_ROW))
         if n >= 2 ** 29:
             assert not is_tile(vi_f.value) and not is_tile(ev_f.value)
-            assert lib.mdp_set_sweep_form(h, mdpvi.FORM_TILE) == mdpvi.EINVAL
+            for form in (mdpvi.FORM_TILE, mdpvi.FORM_ROW):
+                assert lib.mdp_set_sweep_form(h, form) == mdpvi.EINVAL
         else:
             assert is_tile(vi_f.value)
     finally:

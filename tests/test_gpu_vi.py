@@ -245,7 +245,12 @@ FORM_CASES = [("small_parity", W.small_parity()),
               ("tile_auto_K8C3J2", W.make(8, 3, (1, 2), (0.7, 0.4), 0.15, 0.03, (1.0, 2.2), 0.92)),
               # the under-utilisation penalty on the tile form
               ("tile_penalty_K4C9J3", W.make(4, 9, (1, 2, 3), (0.5, 0.4, 0.3), 0.1, 0.02, (1.0, 2.2, 3.1),
-                                             0.95, reject_cost=(0.2, 0.0, 0.1), idle_unit_cost=0.08))]
+                                             0.95, reject_cost=(0.2, 0.0, 0.1), idle_unit_cost=0.08)),
+              # the row form (C = 10, sizes up to 3): penalty and reject costs,
+              # and a single class of the largest size the -inf padding covers
+              ("row_K5C10J3_penalty", W.make(5, 10, (1, 2, 3), (0.6, 0.5, 0.3), 0.1, 0.02, (1.0, 2.2, 3.1), 0.96,
+                                             reject_cost=(0.1, 0.3, 0.2), idle_unit_cost=0.05)),
+              ("row_K5C10J1_s3", W.make(5, 10, (3,), (0.9,), 0.12, 0.03, (2.5,), 0.95))]
 
 def _forms(mdpvi, inst):
     forms = [0]
@@ -261,6 +266,12 @@ def _forms(mdpvi, inst):
         forms += [mdpvi.FORM_TILE, mdpvi.FORM_TILE + 2, mdpvi.FORM_TILE + 5]
     except mdpvi.MdpviError as e:
         assert e.code == mdpvi.EINVAL
+    try:
+        mdp.set_sweep_form(mdpvi.FORM_ROW)
+        # one workgroup per tile; one and three workgroups per CU walking tiles
+        forms += [mdpvi.FORM_ROW, mdpvi.FORM_ROW + 1, mdpvi.FORM_ROW + 3]
+    except mdpvi.MdpviError as e:
+        assert e.code == mdpvi.EINVAL
     return forms
 
 
@@ -272,6 +283,8 @@ def test_sweep_forms_bit_identical(mdpvi, name, inst):
     forms = _forms(mdpvi, inst)
     if name.startswith("tile") or name == "gradient":
         assert mdpvi.FORM_TILE in forms
+    if name.startswith("row") or name == "gradient":
+        assert mdpvi.FORM_ROW in forms
     ref = None
     for f in forms + [-1]:
         mdp.set_sweep_form(f)
@@ -295,7 +308,7 @@ def test_eval_forms_bit_identical(mdpvi, name, inst):
     # the result is the oracle's V_pi
     import torch
     mdp = mdpvi.MDP.from_instance(inst)
-    forms = [f for f in _forms(mdpvi, inst) if f == 0 or f >= mdpvi.FORM_TILE]
+    forms = [f for f in _forms(mdpvi, inst) if f == 0 or mdpvi.FORM_TILE <= f < mdpvi.FORM_ROW]
     pi = mdp.policy_greedy("least_loaded")
     ref = None
     for f in forms + [-1]:
@@ -322,7 +335,7 @@ def test_tile_full_size_matches_direct(mdpvi):
     mdp = mdpvi.MDP.from_instance(inst)
     pi = mdp.policy_greedy("least_loaded")
     outs = {}
-    for f in (0, mdpvi.FORM_TILE, mdpvi.FORM_TILE + 3):
+    for f in (0, mdpvi.FORM_TILE, mdpvi.FORM_TILE + 3, mdpvi.FORM_ROW + 1):
         mdp.set_sweep_form(f)
         V = torch.zeros(mdp.num_states, device="cuda")
         with pytest.raises(mdpvi.MdpviError) as ei:
@@ -334,7 +347,7 @@ def test_tile_full_size_matches_direct(mdpvi):
         assert ei.value.code == mdpvi.ENOCONV
         outs[f] = (V.cpu().numpy().view(np.uint32).copy(), Ve.cpu().numpy().view(np.uint64).copy())
         print(f"large_single form {f}: done", flush=True)
-    for f in (mdpvi.FORM_TILE, mdpvi.FORM_TILE + 3):
+    for f in (mdpvi.FORM_TILE, mdpvi.FORM_TILE + 3, mdpvi.FORM_ROW + 1):
         assert np.array_equal(outs[0][0], outs[f][0])
         assert np.array_equal(outs[0][1], outs[f][1])
 
@@ -349,6 +362,20 @@ def test_k7_beyond_cache_sampled(mdpvi):
     import torch
     inst = W.large_single(K=7)
     mdp = mdpvi.MDP.from_instance(inst)
+    # the automatic form here (beyond the cache: the row form) against the
+    # tile form, bit for bit over 8 sweeps
+    outs = []
+    for f in (-1, mdpvi.FORM_TILE):
+        mdp.set_sweep_form(f)
+        V = torch.zeros(mdp.num_states, device="cuda")
+        with pytest.raises(mdpvi.MdpviError) as ei:
+            mdp.vi_solve(V, tol=1e-30, max_iter=8)
+        assert ei.value.code == mdpvi.ENOCONV
+        outs.append(V.cpu().numpy().view(np.uint32).copy())
+        del V
+    assert np.array_equal(outs[0], outs[1])
+    del outs
+    mdp.set_sweep_form(-1)
     V = torch.zeros(mdp.num_states, device="cuda")
     st = mdp.vi_solve(V, tol=1e-6)
     print(f"K=7: {st['iterations']} sweeps, {st['seconds']:.3f} s, forms {mdp.sweep_forms()}", flush=True)
@@ -394,7 +421,8 @@ def test_tile_orders_bit_identical(mdpvi):
     # (None, -1): the automatic choice, the launch configuration bench.py times
     cases = [(None, 0), (None, -1), ("index", mdpvi.FORM_TILE), ("rcb", mdpvi.FORM_TILE),
              ("deal1", mdpvi.FORM_TILE), ("deal16", mdpvi.FORM_TILE), ("deal7", mdpvi.FORM_TILE + 3),
-             ("rcb", mdpvi.FORM_TILE + 2)]
+             ("rcb", mdpvi.FORM_TILE + 2), ("rcb", mdpvi.FORM_ROW + 1), ("deal16", mdpvi.FORM_ROW),
+             ("index", mdpvi.FORM_ROW + 2)]
     old = os.environ.get("MDPVI_TILE_ORDER")
     try:
         for order, form in cases:
@@ -428,6 +456,10 @@ def test_tile_orders_bit_identical(mdpvi):
 
 
 def test_autotune_cache(mdpvi, tmp_path):
+    """mdp_autotune times value iteration, FP64 evaluation and the adjoint
+    sweep on one handle and records each operation's best form for the
+    shape; a second handle of the same shape then runs those forms in
+    automatic mode, with the same bits as the direct forms."""
     import json
     import os
     import torch
@@ -435,13 +467,31 @@ def test_autotune_cache(mdpvi, tmp_path):
     os.environ["MDPVI_AUTOTUNE_CACHE"] = str(path)
     try:
         inst = W.gradient_instance()
-        mdp = mdpvi.MDP.from_instance(inst)
-        form, us = mdp.autotune(trials=5)
+        a = mdpvi.MDP.from_instance(inst)
+        form, us = a.autotune(trials=5)
         assert form >= 0 and us > 0
         data = json.loads(path.read_text())
-        key = [k for k in data if "K=5|C=10|J=2|S=1,2" in k]
-        assert len(key) == 1 and data[key[0]][0] == form
-        V = torch.zeros(mdp.num_states, device="cuda")
-        mdp.vi_solve(V, tol=1e-6)
+        rec = {}
+        for op in ("vi", "eval", "adjoint"):
+            key = [k for k in data if k.startswith(op + "|") and "K=5|C=10|J=2|S=1,2" in k]
+            assert len(key) == 1, (op, list(data))
+            rec[op] = data[key[0]]
+            print(f"tuned {op}: form {rec[op][0]}, {rec[op][1]:.2f} us per sweep", flush=True)
+        assert rec["vi"][0] == form
+        b = mdpvi.MDP.from_instance(inst)   # another handle of the shape
+        vi_f, ev_f = b.sweep_forms()
+        assert vi_f == rec["vi"][0] and ev_f == rec["eval"][0]
+        assert b.adjoint_form() == rec["adjoint"][0]
+        # the tuned forms compute the direct forms' iterates
+        pi = b.policy_greedy("least_loaded")
+        outs = []
+        for f in (-1, 0):
+            b.set_sweep_form(f)
+            V = torch.zeros(b.num_states, device="cuda")
+            b.vi_solve(V, tol=1e-6)
+            Ve = torch.zeros(b.num_states, dtype=torch.float64, device="cuda")
+            b.policy_eval(pi, Ve, tol=1e-10)
+            outs.append((V.cpu().numpy().view(np.uint32), Ve.cpu().numpy().view(np.uint64)))
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     finally:
         del os.environ["MDPVI_AUTOTUNE_CACHE"]
