@@ -44,7 +44,12 @@ __global__ __launch_bounds__(kBlock) void adjoint_sweep_kernel(Model M, const ui
 #pragma unroll
   for (int i = 0; i < OPT; ++i) {
     const Idx o = base + static_cast<Idx>(i * kBlock);
-    if (o < static_cast<Idx>(M.n_occ)) dsum += adjoint_occupancy<KMAX, JMAX, Idx, EXACT>(M, pi, win, wout, o);
+    if (o < static_cast<Idx>(M.n_occ)) {
+      if constexpr (EXACT)
+        dsum += adjoint_occupancy_exact<KMAX, JMAX>(M, pi, win, wout, static_cast<uint32_t>(o));
+      else
+        dsum += adjoint_occupancy<KMAX, JMAX, Idx>(M, pi, win, wout, o);
+    }
   }
   block_sum_to(dsum, res, j);
 }

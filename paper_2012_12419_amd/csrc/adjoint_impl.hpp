@@ -73,6 +73,90 @@ __device__ __forceinline__ double adjoint_occupancy(const Model& M, const uint8_
   return dsum;
 }
 
+// The same transposed backup for an exact shape (K hosts, J classes known
+// at compile time), with every load issued before the first use: the
+// predecessors' actions and weights are loaded unconditionally (a missing
+// predecessor reads the state itself) and selected afterwards, so a thread
+// waits for one round trip instead of one per predecessor.  Adding the
+// weight of a predecessor that does not apply is adding +0.0 to a sum of
+// non-negative terms and a release from a full host multiplies by 0.0: the
+// sums are those of adjoint_occupancy, term by term and in the same order.
+constexpr int kLineLoads = 16;
+
+template <int K, int J>
+__device__ __forceinline__ double adjoint_occupancy_exact(const Model& M, const uint8_t* __restrict__ pi,
+                                                          const float* __restrict__ win,
+                                                          float* __restrict__ wout, uint32_t o) {
+  const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
+  int n[K];
+  decode<K>(M, o, n);
+  int load = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) load += n[k];
+  uint32_t st[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) st[k] = static_cast<uint32_t>(M.stride[k]);
+  // arrival predecessors: (n', e) itself and (n' - size_e 1_k, e)
+  int p_own[J], p_k[K][J];
+  float w_own[J], w_k[K][J], w_rel[K][J];
+  bool has[K][J];
+#pragma unroll
+  for (int e = 0; e < J; ++e) {
+    const uint32_t s0 = o + e * nocc;
+    p_own[e] = pi[s0];
+    w_own[e] = win[s0];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      has[k][e] = n[k] >= M.size[e];
+      const uint32_t src = has[k][e] ? s0 - static_cast<uint32_t>(M.size[e]) * st[k] : s0;
+      p_k[k][e] = pi[src];
+      w_k[k][e] = win[src];
+      w_rel[k][e] = win[n[k] < M.C ? s0 + st[k] : s0];
+    }
+  }
+  double B = 0.0;
+#pragma unroll
+  for (int e = 0; e < J; ++e) B += p_own[e] == M.K ? static_cast<double>(w_own[e]) : 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int e = 0; e < J; ++e) B += (has[k][e] && p_k[k][e] == k) ? static_cast<double>(w_k[k][e]) : 0.0;
+  }
+  const double idle = M.mu_L * static_cast<double>(M.KC - load);
+  double dsum = 0.0;
+#pragma unroll
+  for (int e = 0; e < J; ++e) {
+    const uint32_t base = o + e * nocc;
+    const float wold = w_own[e];
+    double acc = fma(M.p[e], B, idle * static_cast<double>(wold));
+    double rs = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc = fma(n[k] < M.C ? M.mu_L * (n[k] + 1) : 0.0, static_cast<double>(w_rel[k][e]), acc);
+      if (n[k] == 0) {
+        // the line sum along digit k, in order x = 0..C; lines of up to
+        // kLineLoads values are loaded all at once
+        if (M.C < kLineLoads) {
+          float v[kLineLoads];
+#pragma unroll
+          for (int x = 0; x < kLineLoads; ++x) v[x] = win[base + (x <= M.C ? static_cast<uint32_t>(x) * st[k] : 0u)];
+#pragma unroll
+          for (int x = 0; x < kLineLoads; ++x)
+            if (x <= M.C) rs += static_cast<double>(v[x]);
+        } else {
+          for (int x = 0; x <= M.C; ++x) rs += static_cast<double>(win[base + static_cast<uint32_t>(x) * st[k]]);
+        }
+      }
+    }
+    acc = fma(M.nu_L, rs, acc);
+    const double c = (o == 0) ? M.c_obj[e] : 0.0;
+    const float wn = static_cast<float>(fma(M.gamma, acc, c));
+    wout[base] = wn;
+    dsum += fabs(static_cast<double>(wn) - static_cast<double>(wold));
+  }
+  return dsum;
+}
+
 // Adds the gradient terms of the classes of occupancy o to g[] (layout:
 // lambda at 0..JMAX-1, mu at JMAX, nu at JMAX+1, r at JMAX+2..).
 template <int KMAX, int JMAX, typename Idx>

@@ -136,9 +136,10 @@ def stats_markdown(stats_csv: str, command: str, top: int = 12, trace_csv: str =
 
 
 def run_sweeps(kernel: str, workload: str, sweeps: int, copy_mb: int, form: int) -> None:
-    """`sweeps` sweeps of value iteration (kernel "vi") or of FP64 evaluation
-    of the least-loaded policy (kernel "eval") from zero, then a device copy
-    of copy_mb MiB."""
+    """`sweeps` sweeps of value iteration (kernel "vi"), of FP64 evaluation
+    of the least-loaded policy (kernel "eval") or of the adjoint equation of
+    that policy (kernel "adjoint") from zero, then a device copy of copy_mb
+    MiB."""
     import torch
 
     import paper_2012_12419_amd as mdpvi
@@ -152,6 +153,10 @@ def run_sweeps(kernel: str, workload: str, sweeps: int, copy_mb: int, form: int)
         if kernel == "vi":
             V = torch.zeros(mdp.num_states, device="cuda")
             mdp.vi_solve(V, tol=1e-300, max_iter=sweeps)
+        elif kernel == "adjoint":
+            pi = mdp.policy_greedy("least_loaded")
+            Vp = torch.zeros(mdp.num_states, dtype=torch.float64, device="cuda")
+            mdp.vi_adjoint(pi, Vp, tol=1e-300, max_iter=sweeps)
         else:
             pi = mdp.policy_greedy("least_loaded")
             V = torch.zeros(mdp.num_states, dtype=torch.float64, device="cuda")
@@ -198,7 +203,7 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     r = sub.add_parser("run")
-    r.add_argument("--kernel", choices=["vi", "eval"], default="vi")
+    r.add_argument("--kernel", choices=["vi", "eval", "adjoint"], default="vi")
     r.add_argument("--workload", default="large_single")
     r.add_argument("--sweeps", type=int, default=30)
     r.add_argument("--copy-mb", type=int, default=1024)
