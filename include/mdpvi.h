@@ -61,6 +61,7 @@ extern "C" {
 #define MDPVI_MAX_J 8        /* task classes */
 #define MDPVI_FORM_TILE 16   /* mdp_set_sweep_form: the tile form */
 #define MDPVI_FORM_ROW 32    /* mdp_set_sweep_form: the row form of the tile sweep */
+#define MDPVI_ADJOINT_GROUP 32 /* mdp_set_adjoint_form: the group form of the adjoint sweep */
 
 /* Model parameters (Sec. V-B..V-E).  All pointers are host pointers to J
  * entries, read during mdp_build only.
@@ -367,11 +368,24 @@ int mdp_sweep_forms(mdpvi_mdp_t h, int32_t *vi, int32_t *eval);
 int mdp_autotune(mdpvi_mdp_t h, const float *V, int32_t trials, void *hip_stream,
                  int32_t *best_form, double *best_us);
 
-/* The adjoint sweep form the next vi_adjoint on this handle runs: 16 + OPT
- * for the exact-shape kernels (K in 3..8, J <= 3), OPT for the generic ones,
- * OPT in {1, 2, 4} occupancies per thread (the recorded tuning, else one per
- * thread below 2^21 occupancies and four above); -1 for a NULL handle.      */
+/* The adjoint sweep form the next vi_adjoint on this handle runs:
+ * MDPVI_ADJOINT_GROUP for the group form, 16 + OPT for the exact-shape
+ * kernels (K in 3..8, J <= 3), OPT for the generic ones, OPT in {1, 2, 4}
+ * occupancies per thread.  The form set by mdp_set_adjoint_form, else the
+ * recorded tuning, else the group form where it applies, else the
+ * exact-shape kernels with one occupancy per thread below 2^21 occupancies
+ * and four above, else the generic ones; -1 for a NULL handle.             */
 int32_t mdp_adjoint_form(mdpvi_mdp_t h);
+
+/* Choice of the adjoint sweep kernels for this handle (a tuning knob: every
+ * form gives bit-identical w and gradients).  0: automatic (the default);
+ * MDPVI_ADJOINT_GROUP: the group form (each workgroup takes whole groups of
+ * the (C+1)^2 occupancies that share digits 2..K-1, one occupancy per lane;
+ * neighbours along digits 0 and 1, including the reset line sums of the
+ * transposed backup of Eq. (18), are read from LDS; K in 3..8, J <= 3,
+ * C <= 15, fewer than 2^29 states); 16 + OPT or OPT as for mdp_adjoint_form.
+ * Errors: MDPVI_EINVAL (NULL handle, or a form that does not apply).        */
+int mdp_set_adjoint_form(mdpvi_mdp_t h, int32_t form);
 
 /* Per-sweep kernel timing for the iterative calls of this handle: when on,
  * every sweep launch is bracketed by two HIP events and their elapsed times

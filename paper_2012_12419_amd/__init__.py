@@ -32,6 +32,8 @@ EDEVICE = -5
 ENOMEM = -6
 FORM_TILE = 16   # mdp_set_sweep_form: the tile form
 FORM_ROW = 32    # mdp_set_sweep_form: the row form of the tile sweeps
+ADJOINT_GROUP = 32   # mdp_set_adjoint_form: the group form of the adjoint sweep
+ADJOINT_EXACT = 16   # mdp_set_adjoint_form: exact-shape adjoint kernels (+ occupancies per thread)
 STATIC_PAID = -1    # static placement: the task went to the paid cloud
 STATIC_EMPTY = -2   # static placement: empty task slot (need 0)
 _NAMES = {EINVAL: "EINVAL", ERANGE: "ERANGE", ENOCONV: "ENOCONV", ENAN: "ENAN",
@@ -99,6 +101,7 @@ SIGNATURES = {
     "policy_iteration": (ctypes.c_int, [_vp, _vp, _vp, _c_double, _c_int64, _c_double, _c_int64, _vp,
                                         ctypes.POINTER(Stats), ctypes.POINTER(_c_int64)]),
     "mdp_adjoint_form": (_c_int32, [_vp]),
+    "mdp_set_adjoint_form": (ctypes.c_int, [_vp, _c_int32]),
     "mdp_sweep_forms": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32)]),
     "mdp_autotune": (ctypes.c_int, [_vp, _vp, _c_int32, _vp, ctypes.POINTER(_c_int32),
                                     ctypes.POINTER(_c_double)]),
@@ -229,6 +232,12 @@ class MDP:
     def adjoint_form(self) -> int:
         """The adjoint sweep form the next vi_adjoint runs (mdp_adjoint_form)."""
         return int(load().mdp_adjoint_form(self._h))
+
+    def set_adjoint_form(self, form: int = 0):
+        """0 automatic, ADJOINT_GROUP the group form, ADJOINT_EXACT + t or t
+        (t in 1, 2, 4 occupancies per thread) the exact-shape or generic
+        kernels (mdp_set_adjoint_form)."""
+        _check(load().mdp_set_adjoint_form(self._h, int(form)))
 
     def autotune(self, V=None, trials: int = 10, stream=None):
         """Time every sweep form on this instance; returns (best form, us per sweep)."""

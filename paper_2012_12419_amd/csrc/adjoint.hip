@@ -178,20 +178,23 @@ size_t grad_partial_doubles(const Model& M) {
   return static_cast<size_t>(sweep_blocks(M)) * (2 * (M.J <= 4 ? 4 : 8) + 2);
 }
 
-// Adjoint sweep forms: kAdjointExact + OPT (exact-shape kernels, K in 3..8,
-// J <= 3, OPT occupancies per thread) or OPT alone (the generic kernels);
-// 0 picks the exact form where it applies, with one occupancy per thread
-// below kAdjointWideOcc occupancies and kOccPerThread above.
+// Adjoint sweep forms: kAdjointGroup (adjoint_group.hip), kAdjointExact +
+// OPT (exact-shape kernels, K in 3..8, J <= 3, OPT occupancies per thread)
+// or OPT alone (the generic kernels); 0 picks the group form where it
+// applies, else the exact form, with one occupancy per thread below
+// kAdjointWideOcc occupancies and kOccPerThread above.
 bool adjoint_exact_shape(const Model& M) {
   return M.K >= 3 && M.K <= 8 && M.J >= 1 && M.J <= 3 && use_32bit_index(M);
 }
 
 int adjoint_auto_form(const Model& M) {
+  if (adjoint_group_shape(M)) return kAdjointGroup;
   const int opt = M.n_occ < kAdjointWideOcc ? 1 : kOccPerThread;
   return adjoint_exact_shape(M) ? kAdjointExact + opt : opt;
 }
 
 bool adjoint_form_valid(const Model& M, int form) {
+  if (form == kAdjointGroup) return adjoint_group_shape(M);
   const int opt = form & (kAdjointExact - 1);
   if (opt != 1 && opt != 2 && opt != 4) return false;
   return (form & kAdjointExact) ? adjoint_exact_shape(M) : (form == opt);
@@ -225,6 +228,7 @@ hipError_t launch_adjoint_sweep(const Model& M, int form, const uint8_t* pi, con
                                 Ctl* ctl, double* res, long long j, double tol, hipStream_t s) {
   if (form == 0) form = adjoint_auto_form(M);
   if (!adjoint_form_valid(M, form)) return hipErrorInvalidValue;
+  if (form == kAdjointGroup) return launch_adjoint_group(M, pi, win, wout, ctl, res, j, tol, s);
   const bool exact = (form & kAdjointExact) != 0;
   switch (form & (kAdjointExact - 1)) {
     case 1: return launch_adjoint_opt<1>(M, exact, pi, win, wout, ctl, res, j, tol, s);

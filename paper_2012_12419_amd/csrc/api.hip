@@ -49,6 +49,7 @@ struct mdpvi_mdp {
   size_t aux_bytes = 0;
   double* out_host = nullptr;   // pinned, 2 * kMaxJ + 3 doubles
   bool timing = false;          // bracket every sweep with events
+  int adjoint_form = 0;         // adjoint sweep form: 0 automatic, else a valid form
   int slab_t = -1;              // sweep form: -1 automatic, 0 direct, t > 0 slab of t digits,
                                 // MDPVI_FORM_TILE the tile form
   hipEvent_t* sweep_ev = nullptr;   // 2 * kMaxChunk events (created on demand)
@@ -194,6 +195,8 @@ int cu_count() {
   return cus;
 }
 
+static_assert(MDPVI_ADJOINT_GROUP == mdpvi::kAdjointGroup, "adjoint group form code");
+static_assert(mdpvi::kAdjointGroup > mdpvi::kAdjointExact + 4, "adjoint form codes overlap");
 bool is_tile_form(int f) { return f >= MDPVI_FORM_TILE && f <= MDPVI_FORM_TILE + 8; }
 bool is_row_form(int f) { return f >= MDPVI_FORM_ROW && f <= MDPVI_FORM_ROW + 8; }
 // Workgroups of the column walk with w per CU: a multiple of 8.
@@ -270,9 +273,10 @@ int eval_form(mdpvi_mdp* h, mdpvi::TileShape* S) {
 int eval_run(mdpvi_mdp* h, const uint8_t* pi, double* V, double tol, int64_t max_iter, hipStream_t s,
              mdpvi_stats* st);
 
-// The adjoint sweep form to run: the one mdp_autotune recorded for the
-// shape, else the automatic one.
+// The adjoint sweep form to run: the one set on the handle, else the one
+// mdp_autotune recorded for the shape, else the automatic one.
 int adjoint_form(mdpvi_mdp* h) {
+  if (h->adjoint_form > 0) return h->adjoint_form;
   const int cached = tune_lookup(h->M, "adjoint");
   if (cached > 0 && mdpvi::adjoint_form_valid(h->M, cached)) return cached;
   return mdpvi::adjoint_auto_form(h->M);
@@ -863,6 +867,7 @@ int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream
     }
     tune_record(M, "eval", ebest, ebest_t);
     std::vector<int> aforms;
+    if (mdpvi::adjoint_form_valid(M, mdpvi::kAdjointGroup)) aforms.push_back(mdpvi::kAdjointGroup);
     for (int opt : {1, 2, 4}) {
       if (mdpvi::adjoint_form_valid(M, opt)) aforms.push_back(opt);
       if (mdpvi::adjoint_form_valid(M, mdpvi::kAdjointExact + opt)) aforms.push_back(mdpvi::kAdjointExact + opt);
@@ -890,6 +895,14 @@ int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream
 }
 
 int32_t mdp_adjoint_form(mdpvi_mdp_t h) { return h ? adjoint_form(h) : -1; }
+
+int mdp_set_adjoint_form(mdpvi_mdp_t h, int32_t form) {
+  if (!h) return fail(MDPVI_EINVAL, "NULL handle");
+  if (form != 0 && !mdpvi::adjoint_form_valid(h->M, form))
+    return fail(MDPVI_EINVAL, "adjoint form %d does not apply to this instance", form);
+  h->adjoint_form = form;
+  return MDPVI_OK;
+}
 
 int64_t mdp_num_states(mdpvi_mdp_t h) { return h ? h->M.n_states : -1; }
 int32_t mdp_num_actions(mdpvi_mdp_t h) { return h ? h->M.K + 1 : -1; }

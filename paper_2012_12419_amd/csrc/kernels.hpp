@@ -90,10 +90,17 @@ uint32_t eval_sweep_grid(const Model& M);
 hipError_t launch_greedy(const Model& M, int kind, uint8_t* pi, hipStream_t s);
 
 // One transposed (adjoint) sweep w^{j+1} = c + gamma P_pi^T w^j, 1-norm
-// residual.  form: kAdjointExact + OPT (exact-shape kernels) or OPT (generic
-// kernels), OPT in {1, 2, 4} occupancies per thread; 0 automatic.
+// residual.  form: kAdjointGroup (group form: whole (C+1)^2-occupancy groups
+// per workgroup, low-digit neighbours through LDS), kAdjointExact + OPT
+// (exact-shape kernels) or OPT (generic kernels), OPT in {1, 2, 4}
+// occupancies per thread; 0 automatic.
 constexpr int kAdjointExact = 16;
+constexpr int kAdjointGroup = 32;
 bool adjoint_exact_shape(const Model& M);
+bool adjoint_group_shape(const Model& M);
+hipError_t launch_adjoint_group(const Model& M, const uint8_t* pi, const float* win, float* wout, Ctl* ctl,
+                                double* res, long long j, double tol, hipStream_t s);
+
 int adjoint_auto_form(const Model& M);
 bool adjoint_form_valid(const Model& M, int form);
 hipError_t launch_adjoint_sweep(const Model& M, int form, const uint8_t* pi, const float* win, float* wout,

@@ -135,7 +135,8 @@ def stats_markdown(stats_csv: str, command: str, top: int = 12, trace_csv: str =
     return "\n".join(out) + "\n"
 
 
-def run_sweeps(kernel: str, workload: str, sweeps: int, copy_mb: int, form: int) -> None:
+def run_sweeps(kernel: str, workload: str, sweeps: int, copy_mb: int, form: int,
+               adjoint_form: int = 0) -> None:
     """`sweeps` sweeps of value iteration (kernel "vi"), of FP64 evaluation
     of the least-loaded policy (kernel "eval") or of the adjoint equation of
     that policy (kernel "adjoint") from zero, then a device copy of copy_mb
@@ -149,6 +150,7 @@ def run_sweeps(kernel: str, workload: str, sweeps: int, copy_mb: int, form: int)
             "gradient": W.gradient_instance()}[workload]
     mdp = mdpvi.MDP.from_instance(inst)
     mdp.set_sweep_form(form)
+    mdp.set_adjoint_form(adjoint_form)
     try:
         if kernel == "vi":
             V = torch.zeros(mdp.num_states, device="cuda")
@@ -208,6 +210,7 @@ def main(argv=None) -> int:
     r.add_argument("--sweeps", type=int, default=30)
     r.add_argument("--copy-mb", type=int, default=1024)
     r.add_argument("--form", type=int, default=-1)
+    r.add_argument("--adjoint-form", type=int, default=0)
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--command", required=True)
@@ -227,7 +230,7 @@ def main(argv=None) -> int:
     t.add_argument("--command", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "run":
-        run_sweeps(a.kernel, a.workload, a.sweeps, a.copy_mb, a.form)
+        run_sweeps(a.kernel, a.workload, a.sweeps, a.copy_mb, a.form, a.adjoint_form)
         return 0
     if a.cmd == "stats":
         sys.stdout.write(stats_markdown(a.csv, a.command, trace_csv=a.trace, kernels=a.kernels))

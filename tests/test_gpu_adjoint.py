@@ -192,3 +192,51 @@ def test_autograd_function(mdpvi, name, inst):
     got = np.concatenate([lam.grad.numpy(), [mu.grad.item(), nu.grad.item()], r.grad.numpy()])
     assert np.max(np.abs(got - 2.0 * g_o)) <= 1e-5 * np.max(np.abs(2.0 * g_o))
     assert abs(Jt.item() - vi.objective(inst, vi.policy_eval(inst, pi_o))) <= 1e-9 * abs(Jt.item())
+
+
+FORM_SHAPES = [("gradient_K5C10J2", W.gradient_instance()),
+               ("K3C5J3", W.make(3, 5, (1, 2, 3), (0.5, 0.4, 0.3), 0.12, 0.03, (1.0, 2.2, 3.1), 0.96)),
+               ("K4C15J1", W.make(4, 15, (2,), (2.0,), 0.1, 0.02, (1.0,), 0.97)),
+               ("K6C4J3", W.make(6, 4, (1, 2, 3), (0.9, 0.6, 0.3), 0.1, 0.02, (1.0, 2.0, 3.5), 0.97)),
+               ("K8C3J2", W.make(8, 3, (1, 2), (1.5, 0.8), 0.1, 0.03, (1.0, 2.5), 0.95,
+                                 idle_unit_cost=0.05)),
+               ("K7C2J1", W.make(7, 2, (1,), (1.2,), 0.1, 0.02, (1.0,), 0.96))]
+
+
+@pytest.mark.parametrize("name,inst", FORM_SHAPES, ids=[f[0] for f in FORM_SHAPES])
+def test_adjoint_forms_bit_identical(mdpvi, name, inst):
+    """Every adjoint sweep form (group, exact-shape with 1/2/4 occupancies
+    per thread, generic with 1/4) gives the same w bit for bit and the same
+    gradient, for the least-loaded policy: groups per workgroup from 1
+    (C = 15) to 28 (C = 2), a last workgroup with groups past the end, and
+    lanes past the last whole group."""
+    import torch
+    mdp = mdpvi.MDP.from_instance(inst)
+    pi = mdp.policy_greedy("least_loaded")
+    Vp = torch.zeros(mdp.num_states, dtype=torch.float64, device="cuda")
+    mdp.policy_eval(pi, Vp, tol=1e-11)
+    ref = None
+    for form in (mdpvi.ADJOINT_GROUP, mdpvi.ADJOINT_EXACT + 1, mdpvi.ADJOINT_EXACT + 2,
+                 mdpvi.ADJOINT_EXACT + 4, 1, 4):
+        mdp.set_adjoint_form(form)
+        assert mdp.adjoint_form() == form
+        g, Jv, w, st = mdp.vi_adjoint(pi, Vp, tol=1e-9)
+        got = (np.array(g), Jv, w.cpu().numpy().view(np.uint32).copy(), st["iterations"])
+        if ref is None:
+            ref = got
+            continue
+        assert got[3] == ref[3], (form, got[3], ref[3])
+        assert np.array_equal(got[2], ref[2]), form
+        assert np.array_equal(got[0], ref[0]) and got[1] == ref[1], form
+    mdp.set_adjoint_form(0)
+
+
+def test_adjoint_form_rejected_where_it_does_not_apply(mdpvi):
+    big_c = mdpvi.MDP.from_instance(W.make(3, 16, (1,), (1.0,), 0.1, 0.02, (1.0,), 0.95))
+    with pytest.raises(mdpvi.MdpviError) as e:
+        big_c.set_adjoint_form(mdpvi.ADJOINT_GROUP)
+    assert e.value.code == mdpvi.EINVAL
+    big_c.set_adjoint_form(mdpvi.ADJOINT_EXACT + 1)
+    assert big_c.adjoint_form() == mdpvi.ADJOINT_EXACT + 1
+    with pytest.raises(mdpvi.MdpviError):
+        big_c.set_adjoint_form(3)
