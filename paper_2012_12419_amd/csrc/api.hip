@@ -637,7 +637,8 @@ struct mdpvi_batch {
   double* h_gout = nullptr;         // pinned
   void* W2 = nullptr;               // FP64 ping-pong partner (evaluation), on first use
   mdpvi::BatchCtl* d_ctl = nullptr;
-  int* d_remaining = nullptr;
+  int* d_remaining = nullptr;       // [0] unfinished instances, [1] active tiles after a compaction
+  mdpvi::Tile* d_act[2] = {nullptr, nullptr};   // active-tile lists of the round loops
   mdpvi::BatchOut* d_out = nullptr;
   float* W = nullptr;               // ping-pong partner of the concatenated values
   int* h_remaining = nullptr;       // pinned
@@ -1387,10 +1388,13 @@ int ensure_batch_device(mdpvi_batch* b) {
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_gout), static_cast<size_t>(n) * (2 * MDPVI_MAX_J + 3) * sizeof(double))))
     return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_ctl), std::max(n_ctl, 1) * sizeof(mdpvi::BatchCtl)))) return rc;
-  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_remaining), sizeof(int)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_remaining), 2 * sizeof(int)))) return rc;
+  for (int a = 0; a < 2; ++a)
+    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_act[a]), std::max<size_t>(b->tiles_all.size(), 1) * sizeof(mdpvi::Tile))))
+      return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_out), n * sizeof(mdpvi::BatchOut)))) return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->W), std::max<int64_t>(b->offsets[n], 1) * sizeof(float)))) return rc;
-  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_remaining), sizeof(int), hipHostMallocDefault) != hipSuccess ||
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_remaining), 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&b->h_out), n * sizeof(mdpvi::BatchOut), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&b->h_flags), n * sizeof(int), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&b->h_gout), static_cast<size_t>(n) * (2 * MDPVI_MAX_J + 3) * sizeof(double),
@@ -1505,6 +1509,8 @@ void mdp_free_batch(mdpvi_batch_t b) {
   if (b->h_gout) (void)hipHostFree(b->h_gout);
   (void)hipFree(b->d_ctl);
   (void)hipFree(b->d_remaining);
+  (void)hipFree(b->d_act[0]);
+  (void)hipFree(b->d_act[1]);
   (void)hipFree(b->d_out);
   (void)hipFree(b->W);
   if (b->h_remaining) (void)hipHostFree(b->h_remaining);
@@ -1556,16 +1562,22 @@ int vi_solve_batch(mdpvi_batch_t b, float* V, double tol, int64_t max_iter, void
   int64_t issued = 0;
   if (n_round > 0) {
     int64_t chunk = 8;
+    const mdpvi::Tile* tiles = b->d_tiles;
+    int nt = static_cast<int>(b->tiles.size()), cur = 0;
     while (issued < max_iter) {
       const int64_t m = std::min<int64_t>(chunk, max_iter - issued);
       for (int64_t k = 0; k < m; ++k)
-        HIP_TRY(mdpvi::launch_batch_round(b->d_inst, b->d_tiles, static_cast<int>(b->tiles.size()),
-                                          b->rnd_maxK, b->rnd_maxJ, V, b->W, b->d_ctl, b->d_remaining,
-                                          issued + k, tol, s));
+        HIP_TRY(mdpvi::launch_batch_round(b->d_inst, tiles, nt, b->rnd_maxK, b->rnd_maxJ, V, b->W, b->d_ctl,
+                                          b->d_remaining, issued + k, tol, s));
       issued += m;
-      HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, sizeof(int), hipMemcpyDeviceToHost, s));
+      // drop the tiles of instances that have stopped from the next chunk
+      HIP_TRY(mdpvi::launch_batch_compact(tiles, nt, b->d_ctl, b->d_act[cur], b->d_remaining + 1, s));
+      HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      if (*b->h_remaining <= 0) break;
+      if (b->h_remaining[0] <= 0) break;
+      tiles = b->d_act[cur];
+      nt = b->h_remaining[1];
+      cur ^= 1;
       if (chunk < kMaxChunk) chunk *= 2;
     }
     HIP_TRY(mdpvi::launch_batch_round_finish(b->d_inst, b->d_round, n_round, V, b->W, b->d_ctl, issued,
@@ -1630,7 +1642,8 @@ int batch_check_policy(mdpvi_batch* b, const uint8_t* pi, hipStream_t s, int* ba
   return MDPVI_OK;
 }
 
-// Round-form loop over every instance: `round(j)` enqueues round j, `finish(issued)`
+// Round-form loop over every instance: `round(j, tiles, n)` enqueues round j
+// over the n tiles of the instances still running, `finish(issued)`
 // writes back odd finals and the per-instance outputs.  Fills stats from them.
 template <typename Round, typename Finish>
 int batch_all_rounds(mdpvi_batch* b, double tol, int64_t max_iter, hipStream_t s, mdpvi_stats* st,
@@ -1639,13 +1652,20 @@ int batch_all_rounds(mdpvi_batch* b, double tol, int64_t max_iter, hipStream_t s
   HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_all, b->n, b->d_remaining, b->d_flags, 0, s));
   HIP_TRY(hipEventRecord(b->ev0, s));
   int64_t issued = 0, chunk = 8;
+  const mdpvi::Tile* tiles = b->d_tiles_all;
+  int nt = static_cast<int>(b->tiles_all.size()), cur = 0;
   while (issued < max_iter) {
     const int64_t m = std::min<int64_t>(chunk, max_iter - issued);
-    for (int64_t k = 0; k < m; ++k) HIP_TRY(round(issued + k));
+    for (int64_t k = 0; k < m; ++k) HIP_TRY(round(issued + k, tiles, nt));
     issued += m;
-    HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, sizeof(int), hipMemcpyDeviceToHost, s));
+    // drop the tiles of instances that have stopped from the next chunk
+    HIP_TRY(mdpvi::launch_batch_compact(tiles, nt, b->d_ctl, b->d_act[cur], b->d_remaining + 1, s));
+    HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (*b->h_remaining <= 0) break;
+    if (b->h_remaining[0] <= 0) break;
+    tiles = b->d_act[cur];
+    nt = b->h_remaining[1];
+    cur ^= 1;
     if (chunk < kMaxChunk) chunk *= 2;
   }
   HIP_TRY(finish(issued));
@@ -1739,11 +1759,10 @@ int policy_eval_batch(mdpvi_batch_t b, const uint8_t* pi, double* V, double tol,
   if ((rc = batch_check_policy(b, pi, s, &bad))) return rc;
   if (bad >= 0) return fail(MDPVI_EINVAL, "instance %d: policy has an infeasible action", bad);
   double* W = static_cast<double*>(b->W2);
-  const int nt = static_cast<int>(b->tiles_all.size());
   return batch_all_rounds(
       b, tol, max_iter, s, st, iterations, residuals, 17.0,
-      [&](long long j) {
-        return mdpvi::launch_batch_eval_round(b->d_inst, b->d_tiles_all, nt, b->maxK, b->maxJ, pi, V, W, b->d_ctl,
+      [&](long long j, const mdpvi::Tile* tiles, int n) {
+        return mdpvi::launch_batch_eval_round(b->d_inst, tiles, n, b->maxK, b->maxJ, pi, V, W, b->d_ctl,
                                               b->d_remaining, j, tol, s);
       },
       [&](int64_t issued) {
@@ -1764,8 +1783,8 @@ int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t* pi, const double* V_pi, flo
   const int nt = static_cast<int>(b->tiles_all.size());
   rc = batch_all_rounds(
       b, tol, max_iter, s, st, iterations, nullptr, 9.0,
-      [&](long long j) {
-        return mdpvi::launch_batch_adjoint_round(b->d_inst, b->d_tiles_all, nt, b->maxK, b->maxJ, pi, w, b->W,
+      [&](long long j, const mdpvi::Tile* tiles, int n) {
+        return mdpvi::launch_batch_adjoint_round(b->d_inst, tiles, n, b->maxK, b->maxJ, pi, w, b->W,
                                                  b->d_ctl, b->d_remaining, j, tol, s);
       },
       [&](int64_t issued) {

@@ -85,13 +85,23 @@ __global__ __launch_bounds__(kLdsBlock) void batch_lds_vi_kernel(const BatchInst
 
 // ---------------------------------------------------------------- round form
 
-// Sweep operations of the round form.
+// Sweep operations of the round form: run is the generic backup (bounds
+// KM, JM), run_exact the exact-shape one (K hosts and J classes known at
+// compile time, every load issued before the first use), which gives the
+// same bits; exact_ok tells whether an instance meets run_exact's terms.
 struct VIOp {
   using T = float;
   static constexpr ResKind RK = ResKind::kMax;
   template <int KM, int JM>
   __device__ static double run(const Model& M, const uint8_t*, const T* in, T* out, uint32_t o) {
     return backup_occupancy<KM, JM, uint32_t>(M, in, out, o);
+  }
+  __device__ static bool exact_ok(const Model& M) {
+    return M.n_states < (int64_t{1} << 29) && M.J <= 3 && M.n_sizes == M.J;
+  }
+  template <int K, int J>
+  __device__ static double run_exact(const Model& M, const uint8_t*, const T* in, T* out, uint32_t o) {
+    return backup_exact<K, J>(M, make_view(in, static_cast<uint32_t>(M.n_states) * 4u), out, o);
   }
 };
 struct EvalOp {
@@ -101,6 +111,12 @@ struct EvalOp {
   __device__ static double run(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
     return eval_occupancy<KM, JM, uint32_t>(M, pi, in, out, o);
   }
+  __device__ static bool exact_ok(const Model& M) { return M.n_states < (int64_t{1} << 28) && M.J <= 3; }
+  template <int K, int J>
+  __device__ static double run_exact(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
+    return eval_exact<K, J>(M, make_view(pi, static_cast<uint32_t>(M.n_states)),
+                            make_view(in, static_cast<uint32_t>(M.n_states) * 8u), out, o);
+  }
 };
 struct AdjOp {
   using T = float;
@@ -109,7 +125,15 @@ struct AdjOp {
   __device__ static double run(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
     return adjoint_occupancy<KM, JM, uint32_t>(M, pi, in, out, o);
   }
+  __device__ static bool exact_ok(const Model& M) { return M.J <= 3; }
+  template <int K, int J>
+  __device__ static double run_exact(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
+    return adjoint_occupancy_exact<K, J>(M, pi, in, out, o);
+  }
 };
+
+// Host counts up to which the round kernels carry exact-shape backups.
+constexpr int kBatchExactK = 5;
 
 // Per-instance control of the round form: true (for the whole workgroup) when
 // the instance already stopped.  The leader workgroup of the instance (its
@@ -148,7 +172,29 @@ __device__ __forceinline__ bool inst_stopped(BatchCtl* c, long long j, double to
   return false;
 }
 
-template <class Op, int KMAX, int JMAX>
+// The tile's occupancies through the exact-shape backup of (K, J), reduced
+// as the round kernel reduces them.
+template <class Op, int K, int J>
+__device__ __forceinline__ double round_tile_exact(const Model& M, const uint8_t* p,
+                                                   const typename Op::T* Vin, typename Op::T* Vout,
+                                                   uint32_t first) {
+  double acc = 0.0;
+  for (int k = 0; k < kOccPerThread; ++k) {
+    const uint32_t o = first + threadIdx.x + k * kBlock;
+    if (o < static_cast<uint32_t>(M.n_occ)) {
+      const double d = Op::template run_exact<K, J>(M, p, Vin, Vout, o);
+      if constexpr (Op::RK == ResKind::kMax) acc = (d > acc || d != d) ? d : acc;
+      else acc += d;
+    }
+  }
+  return acc;
+}
+
+// EXACT: instances of up to kBatchExactK hosts and 3 classes that meet
+// Op::exact_ok take the exact-shape backup of their own (K, J) (a uniform
+// branch per workgroup: a tile belongs to one instance); others, and every
+// instance when EXACT is false, the generic one.
+template <class Op, int KMAX, int JMAX, bool EXACT>
 __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __restrict__ insts,
                                                               const Tile* __restrict__ tiles,
                                                               typename Op::T* __restrict__ V,
@@ -166,13 +212,33 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
   T* Vout = ((j & 1) ? V : W) + I.offset;
   const uint8_t* p = pi ? pi + I.offset : nullptr;
   double acc = 0.0;
+  bool done = false;
+  if constexpr (EXACT) {
+    if (Op::exact_ok(M)) {
+      done = true;
+      switch (M.K * 4 + M.J) {
+#define MDPVI_ROUND_CASE(K_, J_) \
+  case K_ * 4 + J_: acc = round_tile_exact<Op, K_, J_>(M, p, Vin, Vout, tile.first); break;
+        MDPVI_ROUND_CASE(1, 1) MDPVI_ROUND_CASE(1, 2) MDPVI_ROUND_CASE(1, 3)
+        MDPVI_ROUND_CASE(2, 1) MDPVI_ROUND_CASE(2, 2) MDPVI_ROUND_CASE(2, 3)
+        MDPVI_ROUND_CASE(3, 1) MDPVI_ROUND_CASE(3, 2) MDPVI_ROUND_CASE(3, 3)
+        MDPVI_ROUND_CASE(4, 1) MDPVI_ROUND_CASE(4, 2) MDPVI_ROUND_CASE(4, 3)
+        MDPVI_ROUND_CASE(5, 1) MDPVI_ROUND_CASE(5, 2) MDPVI_ROUND_CASE(5, 3)
+#undef MDPVI_ROUND_CASE
+        default: done = false;
+      }
+      static_assert(kBatchExactK == 5, "the cases above cover K = 1..kBatchExactK");
+    }
+  }
+  if (!done) {
 #pragma unroll
-  for (int k = 0; k < kOccPerThread; ++k) {
-    const uint32_t o = tile.first + threadIdx.x + k * kBlock;
-    if (o < static_cast<uint32_t>(M.n_occ)) {
-      const double d = Op::template run<KMAX, JMAX>(M, p, Vin, Vout, o);
-      if constexpr (Op::RK == ResKind::kMax) acc = (d > acc || d != d) ? d : acc;
-      else acc += d;
+    for (int k = 0; k < kOccPerThread; ++k) {
+      const uint32_t o = tile.first + threadIdx.x + k * kBlock;
+      if (o < static_cast<uint32_t>(M.n_occ)) {
+        const double d = Op::template run<KMAX, JMAX>(M, p, Vin, Vout, o);
+        if constexpr (Op::RK == ResKind::kMax) acc = (d > acc || d != d) ? d : acc;
+        else acc += d;
+      }
     }
   }
   __shared__ double part[kBlock / kWave];
@@ -234,6 +300,30 @@ __global__ void batch_round_finish_kernel(const BatchInst* __restrict__ insts,
     out[i].residual = r;
   }
 }
+
+// Writes the tiles of `in` whose instance has not stopped to `out` (in no
+// particular order: every tile's work and residual word depend on the tile
+// alone) and their number to *n_out, which must be zero on entry.  One
+// atomic per wavefront.
+__global__ void batch_compact_kernel(const Tile* __restrict__ in, int n_in, const BatchCtl* __restrict__ ctl,
+                                     Tile* __restrict__ out, int* n_out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  Tile tile{};
+  bool keep = false;
+  if (t < n_in) {
+    tile = in[t];
+    keep = load_agent(&ctl[tile.inst].done_iter) < 0;
+  }
+  const unsigned long long mask = __ballot(keep);
+  const int lane = threadIdx.x % kWave;
+  const int before = __popcll(mask & ((1ull << lane) - 1ull));
+  int base = 0;
+  if (lane == 0 && mask != 0ull) base = atomicAdd(n_out, __popcll(mask));
+  base = __shfl(base, 0, kWave);
+  if (keep) out[base + before] = tile;
+}
+
+__global__ void batch_zero_kernel(int* p) { *p = 0; }
 
 __global__ void batch_ctl_init_kernel(BatchCtl* ctl, const int32_t* __restrict__ list, int n_list,
                                       int* remaining, int* flags, int n_flags) {
@@ -412,6 +502,14 @@ hipError_t launch_batch_lds_vi(const BatchInst* insts, const int32_t* list, int 
   });
 }
 
+hipError_t launch_batch_compact(const Tile* in, int n_in, const BatchCtl* ctl, Tile* out, int* n_out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(1), 0, s, n_out);
+  if (n_in > 0)
+    hipLaunchKernelGGL(batch_compact_kernel, dim3((n_in + 255) / 256), dim3(256), 0, s, in, n_in, ctl, out, n_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_ctl_init(BatchCtl* ctl, const int32_t* list, int n_list, int* remaining,
                                  int* flags, int n_flags, hipStream_t s) {
   hipLaunchKernelGGL(batch_ctl_init_kernel, dim3(n_list > 0 ? n_list : 1), dim3(64), 0, s, ctl, list,
@@ -424,10 +522,15 @@ static hipError_t launch_round_t(const BatchInst* insts, const Tile* tiles, int 
                                  int maxJ, typename Op::T* V, typename Op::T* W, const uint8_t* pi,
                                  BatchCtl* ctl, int* remaining, long long j, double tol, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
+  if (maxK <= kBatchExactK && maxJ <= 3) {
+    hipLaunchKernelGGL((batch_round_kernel<Op, 8, 4, true>), dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles,
+                       V, W, pi, ctl, remaining, j, tol);
+    return hipGetLastError();
+  }
   return dispatch_kj_b(maxK, maxJ, [&](auto km, auto jm) {
     constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
-    hipLaunchKernelGGL((batch_round_kernel<Op, KM, JM>), dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles,
-                       V, W, pi, ctl, remaining, j, tol);
+    hipLaunchKernelGGL((batch_round_kernel<Op, KM, JM, false>), dim3(n_tiles), dim3(kBlock), 0, s, insts,
+                       tiles, V, W, pi, ctl, remaining, j, tol);
     return hipGetLastError();
   });
 }

@@ -120,6 +120,10 @@ hipError_t launch_objective(const Model& M, const double* V, double* out, hipStr
 hipError_t launch_batch_lds_vi(const BatchInst* insts, const int32_t* list, int n_list, int maxK,
                                int maxJ, size_t lds_bytes, float* V, double tol, long long max_iter,
                                BatchOut* out, hipStream_t s);
+// The tiles of `in` whose instance has not stopped, into `out`; their count
+// into *n_out.
+hipError_t launch_batch_compact(const Tile* in, int n_in, const BatchCtl* ctl, Tile* out, int* n_out,
+                                hipStream_t s);
 hipError_t launch_batch_ctl_init(BatchCtl* ctl, const int32_t* list, int n_list, int* remaining,
                                  int* flags, int n_flags, hipStream_t s);
 hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
