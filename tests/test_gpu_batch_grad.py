@@ -162,6 +162,8 @@ def test_batch_pipeline_first_256_of_sweep(mdpvi):
         assert np.all(chosen >= Q.max(axis=1) - 1e-9 * scale), i
         assert _adjoint_residual(p, pi_h[sl], w_h[sl]) <= 1e-6 * np.abs(w_h[sl]).sum(), i
         assert _eval_residual(p, pig_h[sl], Vg_h[sl]) <= 1e-10 * np.max(np.abs(Vg_h[sl])), i
+        if i % 32 == 31:
+            print(f"instances 0..{i}: checks hold", flush=True)
     print(f"256 instances: single-instance bit identity and oracle properties hold; "
           f"oracle pipeline on {len(small)} instances", flush=True)
     ref = batch_oracle(small, 512, 3)
