@@ -342,6 +342,30 @@ int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t *pi, const double *V_pi, flo
                      double *grad, double *objective, double tol, int64_t max_iter,
                      void *hip_stream, mdpvi_stats *st, int64_t *iterations);
 
+/* Choice of the round kernels of a batch (a tuning knob: every choice gives
+ * bit-identical results).  op: 0 value iteration, 1 FP64 evaluation,
+ * 2 adjoint.  opt: occupancies per thread of a round kernel (its tiles hold
+ * 256 * opt occupancies of one instance), 1, 2 or 4; 0 automatic (the
+ * default: the choice batch_autotune recorded for this batch's instance
+ * shapes, else 4).  Errors: MDPVI_EINVAL.                                   */
+int batch_set_round_form(mdpvi_batch_t b, int32_t op, int32_t opt);
+
+/* opt[3] (host): the occupancies per thread the next value iteration,
+ * evaluation and adjoint calls on this batch use.  Errors: MDPVI_EINVAL.   */
+int batch_round_forms(mdpvi_batch_t b, int32_t *opt);
+
+/* Times one round of each operation's round kernel with 1, 2 and 4
+ * occupancies per thread over every instance of the batch (trials rounds
+ * each, median; zero inputs and the least-loaded policy, in temporary
+ * buffers) and records the fastest per operation in the tuning cache, keyed
+ * by the architecture and a digest of the instances' (K, C, J, sizes); any
+ * batch of the same instance shapes then uses it.  opt[3], us[3] (host,
+ * nullable): the choices and their median microseconds per round (value
+ * iteration is skipped, and its entries left unchanged, when every instance
+ * is solved in LDS).  Synchronous.  Errors: MDPVI_EINVAL, MDPVI_ENOMEM,
+ * MDPVI_EDEVICE.                                                            */
+int batch_autotune(mdpvi_batch_t b, int32_t trials, void *hip_stream, int32_t *opt, double *us);
+
 /* The forms the next vi_solve and policy_eval on this handle run (after the
  * automatic choice): vi, eval (host, nullable).  A value in 1..K-1 is a slab
  * depth, 0 the direct form (the exact-shape one where it applies),

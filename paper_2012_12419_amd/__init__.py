@@ -95,6 +95,10 @@ SIGNATURES = {
     "vi_adjoint_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_c_double),
                                         ctypes.POINTER(_c_double), _c_double, _c_int64, _vp,
                                         ctypes.POINTER(Stats), ctypes.POINTER(_c_int64)]),
+    "batch_set_round_form": (ctypes.c_int, [_vp, _c_int32, _c_int32]),
+    "batch_round_forms": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int32)]),
+    "batch_autotune": (ctypes.c_int, [_vp, _c_int32, _vp, ctypes.POINTER(_c_int32),
+                                      ctypes.POINTER(_c_double)]),
     "mdp_set_timing": (ctypes.c_int, [_vp, _c_int32]),
     "mdp_set_sweep_form": (ctypes.c_int, [_vp, _c_int32]),
     "vi_solve_bsdi": (ctypes.c_int, [_vp, _vp, _c_double, _c_int64, _c_int32, _vp, ctypes.POINTER(Stats)]),
@@ -393,6 +397,27 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    ROUND_OPS = {"vi": 0, "eval": 1, "adjoint": 2}
+
+    def set_round_form(self, op: str, opt: int = 0):
+        """Occupancies per thread (1, 2 or 4; 0 automatic) of the round
+        kernels of op ("vi", "eval" or "adjoint")."""
+        _check(load().batch_set_round_form(self._h, self.ROUND_OPS[op], int(opt)))
+
+    def round_forms(self) -> dict:
+        """The occupancies per thread the next calls use, per operation."""
+        out = (_c_int32 * 3)()
+        _check(load().batch_round_forms(self._h, out))
+        return {k: int(out[v]) for k, v in self.ROUND_OPS.items()}
+
+    def autotune(self, trials: int = 5, stream=None) -> dict:
+        """Time the round kernels with 1, 2 and 4 occupancies per thread and
+        record the fastest per operation; returns {op: (opt, us per round)}."""
+        opt = (_c_int32 * 3)(0, 0, 0)
+        us = (_c_double * 3)(0.0, 0.0, 0.0)
+        _check(load().batch_autotune(self._h, int(trials), _stream_ptr(stream), opt, us))
+        return {k: (int(opt[v]), float(us[v])) for k, v in self.ROUND_OPS.items()}
 
     def vi_solve(self, V, tol: float = 1e-6, max_iter: int = 1_000_000, stream=None):
         """Returns (stats, iterations[n], residuals[n])."""

@@ -453,7 +453,7 @@ std::mutex g_tune_mu;
 std::map<std::string, std::pair<int, double>> g_tune;
 bool g_tune_loaded = false;
 
-std::string tune_key(const Model& M, const char* op) {
+std::string tune_arch() {
   int dev = 0;
   hipDeviceProp_t prop;
   std::string arch = "unknown";
@@ -462,8 +462,12 @@ std::string tune_key(const Model& M, const char* op) {
     const size_t colon = arch.find(':');
     if (colon != std::string::npos) arch = arch.substr(0, colon);
   }
+  return arch;
+}
+
+std::string tune_key(const Model& M, const char* op) {
   std::ostringstream k;
-  k << op << "|" << arch << "|K=" << M.K << "|C=" << M.C << "|J=" << M.J << "|S=";
+  k << op << "|" << tune_arch() << "|K=" << M.K << "|C=" << M.C << "|J=" << M.J << "|S=";
   for (int j = 0; j < M.J; ++j) k << (j ? "," : "") << M.size[j];
   return k.str();
 }
@@ -515,6 +519,20 @@ int tune_lookup(const Model& M, const char* op) {
   tune_load_locked();
   auto it = g_tune.find(tune_key(M, op));
   return it == g_tune.end() ? -2 : it->second.first;
+}
+
+int tune_lookup_key(const std::string& key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(key);
+  return it == g_tune.end() ? -2 : it->second.first;
+}
+
+void tune_record_key(const std::string& key, int form, double us) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tune[key] = {form, us};
+  tune_store_locked();
 }
 
 void tune_record(const Model& M, const char* op, int form, double us) {
@@ -620,6 +638,13 @@ struct mdpvi_batch {
   std::vector<mdpvi::Tile> tiles;        // round-form instances (value iteration)
   std::vector<mdpvi::Tile> tiles_all;    // every instance (other passes)
   std::vector<int32_t> tile_begin;       // n+1 offsets of each instance in tiles_all
+  // tiles of the round loops with 1, 2 and 4 occupancies per thread (index
+  // log2 of that count): round-form instances, and every instance
+  std::vector<mdpvi::Tile> rtiles[3], rtiles_all[3];
+  mdpvi::Tile* d_rtiles[3] = {nullptr, nullptr, nullptr};
+  mdpvi::Tile* d_rtiles_all[3] = {nullptr, nullptr, nullptr};
+  int round_opt[3] = {0, 0, 0};          // per operation (value iteration, evaluation, adjoint):
+                                         // occupancies per thread, 0 automatic
   int lds_maxK = 1, lds_maxJ = 1, rnd_maxK = 1, rnd_maxJ = 1, maxK = 1, maxJ = 1;
   size_t lds_bytes = 0;
   int device = -1;
@@ -1345,6 +1370,43 @@ int policy_greedy(mdpvi_mdp_t h, int32_t kind, uint8_t* pi, void* hip_stream) {
 
 namespace {
 
+// Tuning-cache key of a batch's round kernels for operation op (0 value
+// iteration, 1 evaluation, 2 adjoint): the architecture, the instance count
+// and an FNV-1a digest of every instance's (K, C, J, sizes).
+std::string batch_tune_key(const mdpvi_batch* b, int op) {
+  static const char* const names[3] = {"batch-vi", "batch-eval", "batch-adjoint"};
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int byte = 0; byte < 8; ++byte) {
+      h ^= static_cast<uint64_t>(v >> (8 * byte)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  for (const Model& M : b->models) {
+    mix(M.K);
+    mix(M.C);
+    mix(M.J);
+    for (int j = 0; j < M.J; ++j) mix(M.size[j]);
+  }
+  char buf[32];
+  std::snprintf(buf, sizeof buf, "%016llx", static_cast<unsigned long long>(h));
+  std::ostringstream k;
+  k << names[op] << "|" << tune_arch() << "|n=" << b->n << "|shapes=" << buf;
+  return k.str();
+}
+
+// Occupancies per thread of the round kernels of operation op: the one set
+// on the batch, else the one batch_autotune recorded for its shapes, else
+// kOccPerThread.
+int batch_opt(const mdpvi_batch* b, int op) {
+  if (b->round_opt[op] > 0) return b->round_opt[op];
+  const int cached = tune_lookup_key(batch_tune_key(b, op));
+  if (cached == 1 || cached == 2 || cached == 4) return cached;
+  return mdpvi::kOccPerThread;
+}
+
+int opt_index(int opt) { return opt == 1 ? 0 : opt == 2 ? 1 : 2; }
+
 int ensure_batch_device(mdpvi_batch* b) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -1390,8 +1452,15 @@ int ensure_batch_device(mdpvi_batch* b) {
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_ctl), std::max(n_ctl, 1) * sizeof(mdpvi::BatchCtl)))) return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_remaining), 2 * sizeof(int)))) return rc;
   for (int a = 0; a < 2; ++a)
-    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_act[a]), std::max<size_t>(b->tiles_all.size(), 1) * sizeof(mdpvi::Tile))))
+    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_act[a]),
+                     std::max<size_t>(b->rtiles_all[0].size(), 1) * sizeof(mdpvi::Tile))))
       return rc;
+  for (int oi = 0; oi < 3; ++oi) {
+    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_rtiles[oi]), b->rtiles[oi].size() * sizeof(mdpvi::Tile))))
+      return rc;
+    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_rtiles_all[oi]), b->rtiles_all[oi].size() * sizeof(mdpvi::Tile))))
+      return rc;
+  }
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_out), n * sizeof(mdpvi::BatchOut)))) return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->W), std::max<int64_t>(b->offsets[n], 1) * sizeof(float)))) return rc;
   if (hipHostMalloc(reinterpret_cast<void**>(&b->h_remaining), 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
@@ -1409,6 +1478,13 @@ int ensure_batch_device(mdpvi_batch* b) {
     HIP_TRY(hipMemcpy(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(mdpvi::Tile), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_tiles_all, b->tiles_all.data(), b->tiles_all.size() * sizeof(mdpvi::Tile),
                     hipMemcpyHostToDevice));
+  for (int oi = 0; oi < 3; ++oi) {
+    if (!b->rtiles[oi].empty())
+      HIP_TRY(hipMemcpy(b->d_rtiles[oi], b->rtiles[oi].data(), b->rtiles[oi].size() * sizeof(mdpvi::Tile),
+                        hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_rtiles_all[oi], b->rtiles_all[oi].data(), b->rtiles_all[oi].size() * sizeof(mdpvi::Tile),
+                      hipMemcpyHostToDevice));
+  }
   HIP_TRY(hipMemcpy(b->d_all, b->all_list.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_tile_begin, b->tile_begin.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
@@ -1484,6 +1560,17 @@ int mdp_build_batch(const mdpvi_params* p, int32_t n, mdpvi_batch_t* out) {
     for (uint32_t t = 0; t < static_cast<uint32_t>(M.n_occ); t += per) b->tiles_all.push_back({i, t});
     b->tile_begin.push_back(static_cast<int32_t>(b->tiles_all.size()));
   }
+  for (int oi = 0; oi < 3; ++oi) {
+    const uint32_t per = static_cast<uint32_t>(mdpvi::kBlock) << oi;
+    for (int i = 0; i < n; ++i) {
+      const uint32_t n_occ = static_cast<uint32_t>(b->models[i].n_occ);
+      const bool in_round = b->models[i].n_states > lds_states;
+      for (uint32_t t = 0; t < n_occ; t += per) {
+        if (in_round) b->rtiles[oi].push_back({i, t});
+        b->rtiles_all[oi].push_back({i, t});
+      }
+    }
+  }
   std::sort(cost.begin(), cost.end(), [](auto& x, auto& y) { return x.first > y.first; });
   for (auto& c : cost) b->lds_list.push_back(c.second);
   b->lds_bytes = static_cast<size_t>(2 * max_lds_n) * sizeof(float);
@@ -1511,6 +1598,10 @@ void mdp_free_batch(mdpvi_batch_t b) {
   (void)hipFree(b->d_remaining);
   (void)hipFree(b->d_act[0]);
   (void)hipFree(b->d_act[1]);
+  for (int oi = 0; oi < 3; ++oi) {
+    (void)hipFree(b->d_rtiles[oi]);
+    (void)hipFree(b->d_rtiles_all[oi]);
+  }
   (void)hipFree(b->d_out);
   (void)hipFree(b->W);
   if (b->h_remaining) (void)hipHostFree(b->h_remaining);
@@ -1562,13 +1653,14 @@ int vi_solve_batch(mdpvi_batch_t b, float* V, double tol, int64_t max_iter, void
   int64_t issued = 0;
   if (n_round > 0) {
     int64_t chunk = 8;
-    const mdpvi::Tile* tiles = b->d_tiles;
-    int nt = static_cast<int>(b->tiles.size()), cur = 0;
+    const int opt = batch_opt(b, 0);
+    const mdpvi::Tile* tiles = b->d_rtiles[opt_index(opt)];
+    int nt = static_cast<int>(b->rtiles[opt_index(opt)].size()), cur = 0;
     while (issued < max_iter) {
       const int64_t m = std::min<int64_t>(chunk, max_iter - issued);
       for (int64_t k = 0; k < m; ++k)
         HIP_TRY(mdpvi::launch_batch_round(b->d_inst, tiles, nt, b->rnd_maxK, b->rnd_maxJ, V, b->W, b->d_ctl,
-                                          b->d_remaining, issued + k, tol, s));
+                                          b->d_remaining, issued + k, tol, opt, s));
       issued += m;
       // drop the tiles of instances that have stopped from the next chunk
       HIP_TRY(mdpvi::launch_batch_compact(tiles, nt, b->d_ctl, b->d_act[cur], b->d_remaining + 1, s));
@@ -1646,14 +1738,14 @@ int batch_check_policy(mdpvi_batch* b, const uint8_t* pi, hipStream_t s, int* ba
 // over the n tiles of the instances still running, `finish(issued)`
 // writes back odd finals and the per-instance outputs.  Fills stats from them.
 template <typename Round, typename Finish>
-int batch_all_rounds(mdpvi_batch* b, double tol, int64_t max_iter, hipStream_t s, mdpvi_stats* st,
+int batch_all_rounds(mdpvi_batch* b, int opt, double tol, int64_t max_iter, hipStream_t s, mdpvi_stats* st,
                      int64_t* iterations, double* residuals, double bytes_per_state, Round round,
                      Finish finish) {
   HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_all, b->n, b->d_remaining, b->d_flags, 0, s));
   HIP_TRY(hipEventRecord(b->ev0, s));
   int64_t issued = 0, chunk = 8;
-  const mdpvi::Tile* tiles = b->d_tiles_all;
-  int nt = static_cast<int>(b->tiles_all.size()), cur = 0;
+  const mdpvi::Tile* tiles = b->d_rtiles_all[opt_index(opt)];
+  int nt = static_cast<int>(b->rtiles_all[opt_index(opt)].size()), cur = 0;
   while (issued < max_iter) {
     const int64_t m = std::min<int64_t>(chunk, max_iter - issued);
     for (int64_t k = 0; k < m; ++k) HIP_TRY(round(issued + k, tiles, nt));
@@ -1759,11 +1851,12 @@ int policy_eval_batch(mdpvi_batch_t b, const uint8_t* pi, double* V, double tol,
   if ((rc = batch_check_policy(b, pi, s, &bad))) return rc;
   if (bad >= 0) return fail(MDPVI_EINVAL, "instance %d: policy has an infeasible action", bad);
   double* W = static_cast<double*>(b->W2);
+  const int opt = batch_opt(b, 1);
   return batch_all_rounds(
-      b, tol, max_iter, s, st, iterations, residuals, 17.0,
+      b, opt, tol, max_iter, s, st, iterations, residuals, 17.0,
       [&](long long j, const mdpvi::Tile* tiles, int n) {
         return mdpvi::launch_batch_eval_round(b->d_inst, tiles, n, b->maxK, b->maxJ, pi, V, W, b->d_ctl,
-                                              b->d_remaining, j, tol, s);
+                                              b->d_remaining, j, tol, opt, s);
       },
       [&](int64_t issued) {
         return mdpvi::launch_batch_eval_finish(b->d_inst, b->d_all, b->n, V, W, b->d_ctl, issued, b->d_out, s);
@@ -1781,11 +1874,12 @@ int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t* pi, const double* V_pi, flo
   if ((rc = batch_check_policy(b, pi, s, &bad))) return rc;
   if (bad >= 0) return fail(MDPVI_EINVAL, "instance %d: policy has an infeasible action", bad);
   const int nt = static_cast<int>(b->tiles_all.size());
+  const int opt = batch_opt(b, 2);
   rc = batch_all_rounds(
-      b, tol, max_iter, s, st, iterations, nullptr, 9.0,
+      b, opt, tol, max_iter, s, st, iterations, nullptr, 9.0,
       [&](long long j, const mdpvi::Tile* tiles, int n) {
         return mdpvi::launch_batch_adjoint_round(b->d_inst, tiles, n, b->maxK, b->maxJ, pi, w, b->W,
-                                                 b->d_ctl, b->d_remaining, j, tol, s);
+                                                 b->d_ctl, b->d_remaining, j, tol, opt, s);
       },
       [&](int64_t issued) {
         return mdpvi::launch_batch_adjoint_finish(b->d_inst, b->d_all, b->n, w, b->W, b->d_ctl, issued, b->d_out,
@@ -1804,6 +1898,96 @@ int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t* pi, const double* V_pi, flo
     at += nth;
     if (objective) objective[i] = b->h_gout[i * row + nth];
   }
+  return rc;
+}
+
+int batch_set_round_form(mdpvi_batch_t b, int32_t op, int32_t opt) {
+  if (!b) return fail(MDPVI_EINVAL, "NULL batch");
+  if (op < 0 || op > 2) return fail(MDPVI_EINVAL, "operation %d outside 0..2", op);
+  if (opt != 0 && opt != 1 && opt != 2 && opt != 4)
+    return fail(MDPVI_EINVAL, "occupancies per thread %d not in {0, 1, 2, 4}", opt);
+  b->round_opt[op] = opt;
+  return MDPVI_OK;
+}
+
+int batch_round_forms(mdpvi_batch_t b, int32_t* opt) {
+  if (!b || !opt) return fail(MDPVI_EINVAL, "NULL batch or output");
+  for (int op = 0; op < 3; ++op) opt[op] = batch_opt(b, op);
+  return MDPVI_OK;
+}
+
+int batch_autotune(mdpvi_batch_t b, int32_t trials, void* hip_stream, int32_t* opt, double* us) {
+  if (!b) return fail(MDPVI_EINVAL, "NULL batch");
+  if (trials < 1 || trials > 1000) return fail(MDPVI_EINVAL, "trials=%d outside [1, 1000]", trials);
+  int rc = ensure_batch_device(b);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int64_t N = std::max<int64_t>(b->offsets[b->n], 1);
+  // inputs of the timed rounds: zero values and weights, the least-loaded
+  // policy (feasible everywhere)
+  float* v32 = nullptr;
+  double* v64 = nullptr;
+  double* w64 = nullptr;
+  uint8_t* pol = nullptr;
+  auto release = [&]() {
+    (void)hipFree(v32);
+    (void)hipFree(v64);
+    (void)hipFree(w64);
+    (void)hipFree(pol);
+  };
+  if (hipMalloc(&v32, N * sizeof(float)) != hipSuccess || hipMalloc(&v64, N * sizeof(double)) != hipSuccess ||
+      hipMalloc(&w64, N * sizeof(double)) != hipSuccess || hipMalloc(&pol, N) != hipSuccess) {
+    release();
+    return fail(MDPVI_ENOMEM, "hipMalloc of the tuning buffers failed");
+  }
+  auto run = [&]() -> int {
+    HIP_TRY(hipMemsetAsync(v32, 0, N * sizeof(float), s));
+    HIP_TRY(hipMemsetAsync(v64, 0, N * sizeof(double), s));
+    HIP_TRY(mdpvi::launch_batch_greedy(b->d_inst, b->d_tiles_all, static_cast<int>(b->tiles_all.size()), b->maxK,
+                                       b->maxJ, 0, pol, s));
+    for (int op = 0; op < 3; ++op) {
+      const bool vi = op == 0;
+      if (vi && b->rtiles[0].empty()) continue;   // every instance is solved in LDS
+      int best = mdpvi::kOccPerThread;
+      double best_us = 1e300;
+      for (int oi = 0; oi < 3; ++oi) {
+        const int o = 1 << oi;
+        const mdpvi::Tile* tiles = vi ? b->d_rtiles[oi] : b->d_rtiles_all[oi];
+        const int nt = static_cast<int>(vi ? b->rtiles[oi].size() : b->rtiles_all[oi].size());
+        auto round = [&]() -> hipError_t {
+          if (op == 0)
+            return mdpvi::launch_batch_round(b->d_inst, tiles, nt, b->rnd_maxK, b->rnd_maxJ, v32, b->W, b->d_ctl,
+                                             b->d_remaining, 0, 1.0, o, s);
+          if (op == 1)
+            return mdpvi::launch_batch_eval_round(b->d_inst, tiles, nt, b->maxK, b->maxJ, pol, v64, w64, b->d_ctl,
+                                                  b->d_remaining, 0, 1.0, o, s);
+          return mdpvi::launch_batch_adjoint_round(b->d_inst, tiles, nt, b->maxK, b->maxJ, pol, v32, b->W,
+                                                   b->d_ctl, b->d_remaining, 0, 1.0, o, s);
+        };
+        std::vector<float> ms(trials);
+        for (int r = -1; r < trials; ++r) {   // r = -1: untimed first launch
+          HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_all, b->n, b->d_remaining, b->d_flags, 0, s));
+          HIP_TRY(hipEventRecord(b->ev0, s));
+          HIP_TRY(round());
+          HIP_TRY(hipEventRecord(b->ev1, s));
+          HIP_TRY(hipEventSynchronize(b->ev1));
+          if (r >= 0) HIP_TRY(hipEventElapsedTime(&ms[r], b->ev0, b->ev1));
+        }
+        std::sort(ms.begin(), ms.end());
+        const double t = ms[trials / 2] * 1e3;
+        if (t < best_us) {
+          best_us = t;
+          best = o;
+        }
+      }
+      tune_record_key(batch_tune_key(b, op), best, best_us);
+      if (opt) opt[op] = best;
+      if (us) us[op] = best_us;
+    }
+    return MDPVI_OK;
+  };
+  rc = run();
+  release();
   return rc;
 }
 

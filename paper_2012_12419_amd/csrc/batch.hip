@@ -177,9 +177,9 @@ __device__ __forceinline__ bool inst_stopped(BatchCtl* c, long long j, double to
 template <class Op, int K, int J>
 __device__ __forceinline__ double round_tile_exact(const Model& M, const uint8_t* p,
                                                    const typename Op::T* Vin, typename Op::T* Vout,
-                                                   uint32_t first) {
+                                                   uint32_t first, int opt) {
   double acc = 0.0;
-  for (int k = 0; k < kOccPerThread; ++k) {
+  for (int k = 0; k < opt; ++k) {
     const uint32_t o = first + threadIdx.x + k * kBlock;
     if (o < static_cast<uint32_t>(M.n_occ)) {
       const double d = Op::template run_exact<K, J>(M, p, Vin, Vout, o);
@@ -193,7 +193,8 @@ __device__ __forceinline__ double round_tile_exact(const Model& M, const uint8_t
 // EXACT: instances of up to kBatchExactK hosts and 3 classes that meet
 // Op::exact_ok take the exact-shape backup of their own (K, J) (a uniform
 // branch per workgroup: a tile belongs to one instance); others, and every
-// instance when EXACT is false, the generic one.
+// instance when EXACT is false, the generic one.  A tile holds kBlock * opt
+// occupancies, opt per thread (opt in 1..kOccPerThread).
 template <class Op, int KMAX, int JMAX, bool EXACT>
 __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __restrict__ insts,
                                                               const Tile* __restrict__ tiles,
@@ -201,7 +202,8 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
                                                               typename Op::T* __restrict__ W,
                                                               const uint8_t* __restrict__ pi,
                                                               BatchCtl* __restrict__ ctl,
-                                                              int* remaining, long long j, double tol) {
+                                                              int* remaining, long long j, double tol,
+                                                              int opt) {
   using T = typename Op::T;
   const Tile tile = tiles[blockIdx.x];
   const BatchInst& I = insts[tile.inst];
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
       done = true;
       switch (M.K * 4 + M.J) {
 #define MDPVI_ROUND_CASE(K_, J_) \
-  case K_ * 4 + J_: acc = round_tile_exact<Op, K_, J_>(M, p, Vin, Vout, tile.first); break;
+  case K_ * 4 + J_: acc = round_tile_exact<Op, K_, J_>(M, p, Vin, Vout, tile.first, opt); break;
         MDPVI_ROUND_CASE(1, 1) MDPVI_ROUND_CASE(1, 2) MDPVI_ROUND_CASE(1, 3)
         MDPVI_ROUND_CASE(2, 1) MDPVI_ROUND_CASE(2, 2) MDPVI_ROUND_CASE(2, 3)
         MDPVI_ROUND_CASE(3, 1) MDPVI_ROUND_CASE(3, 2) MDPVI_ROUND_CASE(3, 3)
@@ -231,8 +233,7 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
     }
   }
   if (!done) {
-#pragma unroll
-    for (int k = 0; k < kOccPerThread; ++k) {
+    for (int k = 0; k < opt; ++k) {
       const uint32_t o = tile.first + threadIdx.x + k * kBlock;
       if (o < static_cast<uint32_t>(M.n_occ)) {
         const double d = Op::template run<KMAX, JMAX>(M, p, Vin, Vout, o);
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
       if constexpr (Op::RK == ResKind::kMax) m = (part[w] > m || part[w] != part[w]) ? part[w] : m;
       else m += part[w];
     }
-    unsigned long long* word = &c->res[j % kResSlots][(tile.first / (kBlock * kOccPerThread)) % kBatchLanes][0];
+    unsigned long long* word = &c->res[j % kResSlots][(tile.first / kBlock) % kBatchLanes][0];
     if (m != 0.0) {
       if constexpr (Op::RK == ResKind::kMax)
         atomicMax(word, static_cast<unsigned long long>(__double_as_longlong(m)));
@@ -520,37 +521,39 @@ hipError_t launch_batch_ctl_init(BatchCtl* ctl, const int32_t* list, int n_list,
 template <class Op>
 static hipError_t launch_round_t(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                  int maxJ, typename Op::T* V, typename Op::T* W, const uint8_t* pi,
-                                 BatchCtl* ctl, int* remaining, long long j, double tol, hipStream_t s) {
+                                 BatchCtl* ctl, int* remaining, long long j, double tol, int opt,
+                                 hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
+  if (opt < 1 || opt > kOccPerThread) return hipErrorInvalidValue;
   if (maxK <= kBatchExactK && maxJ <= 3) {
     hipLaunchKernelGGL((batch_round_kernel<Op, 8, 4, true>), dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles,
-                       V, W, pi, ctl, remaining, j, tol);
+                       V, W, pi, ctl, remaining, j, tol, opt);
     return hipGetLastError();
   }
   return dispatch_kj_b(maxK, maxJ, [&](auto km, auto jm) {
     constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
     hipLaunchKernelGGL((batch_round_kernel<Op, KM, JM, false>), dim3(n_tiles), dim3(kBlock), 0, s, insts,
-                       tiles, V, W, pi, ctl, remaining, j, tol);
+                       tiles, V, W, pi, ctl, remaining, j, tol, opt);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                               int maxJ, float* V, float* W, BatchCtl* ctl, int* remaining,
-                              long long j, double tol, hipStream_t s) {
-  return launch_round_t<VIOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, nullptr, ctl, remaining, j, tol, s);
+                              long long j, double tol, int opt, hipStream_t s) {
+  return launch_round_t<VIOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, nullptr, ctl, remaining, j, tol, opt, s);
 }
 
 hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                    int maxJ, const uint8_t* pi, double* V, double* W, BatchCtl* ctl,
-                                   int* remaining, long long j, double tol, hipStream_t s) {
-  return launch_round_t<EvalOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, pi, ctl, remaining, j, tol, s);
+                                   int* remaining, long long j, double tol, int opt, hipStream_t s) {
+  return launch_round_t<EvalOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, pi, ctl, remaining, j, tol, opt, s);
 }
 
 hipError_t launch_batch_adjoint_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                       int maxJ, const uint8_t* pi, float* w, float* W, BatchCtl* ctl,
-                                      int* remaining, long long j, double tol, hipStream_t s) {
-  return launch_round_t<AdjOp>(insts, tiles, n_tiles, maxK, maxJ, w, W, pi, ctl, remaining, j, tol, s);
+                                      int* remaining, long long j, double tol, int opt, hipStream_t s) {
+  return launch_round_t<AdjOp>(insts, tiles, n_tiles, maxK, maxJ, w, W, pi, ctl, remaining, j, tol, opt, s);
 }
 
 template <typename T, ResKind RK>

@@ -126,15 +126,17 @@ hipError_t launch_batch_compact(const Tile* in, int n_in, const BatchCtl* ctl, T
                                 hipStream_t s);
 hipError_t launch_batch_ctl_init(BatchCtl* ctl, const int32_t* list, int n_list, int* remaining,
                                  int* flags, int n_flags, hipStream_t s);
+// One round of value iteration, FP64 evaluation or the adjoint over the
+// given tiles (kBlock * opt occupancies each, opt in 1..kOccPerThread).
 hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                               int maxJ, float* V, float* W, BatchCtl* ctl, int* remaining,
-                              long long j, double tol, hipStream_t s);
+                              long long j, double tol, int opt, hipStream_t s);
 hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                    int maxJ, const uint8_t* pi, double* V, double* W, BatchCtl* ctl,
-                                   int* remaining, long long j, double tol, hipStream_t s);
+                                   int* remaining, long long j, double tol, int opt, hipStream_t s);
 hipError_t launch_batch_adjoint_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                       int maxJ, const uint8_t* pi, float* w, float* W, BatchCtl* ctl,
-                                      int* remaining, long long j, double tol, hipStream_t s);
+                                      int* remaining, long long j, double tol, int opt, hipStream_t s);
 hipError_t launch_batch_round_finish(const BatchInst* insts, const int32_t* list, int n_list,
                                      float* V, const float* W, BatchCtl* ctl, long long issued,
                                      BatchOut* out, hipStream_t s);

@@ -89,3 +89,52 @@ def test_batch_equals_per_instance(mdpvi):
         assert excess <= 1e-6, (i, p.K, p.C, p.J, excess)
         worst = max(worst, excess)
     print(f"all 512 bit-identical; largest fixed-point excess over half an ulp {worst:.2e}", flush=True)
+
+
+def _round_forms_cases():
+    base = [W.make(4, 12, (1, 1), (0.6, 0.4), 0.1, 0.02, (1.0, 1.3), 0.95),     # repeated sizes, 57,122 states
+            W.make(5, 6, (1, 2, 3), (0.9, 0.4, 0.3), 0.1, 0.02, (1.0, 2.4, 3.1), 0.96),  # 50,421
+            W.make(3, 4, (1, 2), (0.8, 0.3), 0.1, 0.02, (1.0, 2.4), 0.94)]     # 250: LDS-resident
+    return {"exact_kernel": base + list(W.batch(6, seed=11)),
+            "generic_kernel": base + [W.make(6, 5, (1,), (1.1,), 0.1, 0.02, (1.0,), 0.95)]}  # K=6: 46,656
+
+
+@pytest.mark.parametrize("case", ["exact_kernel", "generic_kernel"])
+def test_batch_round_forms_bit_identical_and_tuned(mdpvi, case):
+    """Round kernels with 1, 2 and 4 occupancies per thread give the same bits
+    for value iteration, FP64 evaluation and the adjoint (instances of up to
+    5 hosts through the exact-shape backups, with a repeated task size taking
+    the generic one inside them; a 6-host instance sends the batch to the
+    generic kernels); batch_autotune records a choice per operation that a
+    second batch of the same instance shapes then uses."""
+    import torch
+    insts = _round_forms_cases()[case]
+    b = mdpvi.Batch(insts)
+    lb = torch.zeros(b.num_states, device="cuda")
+    for i, p in enumerate(insts):
+        lb[b.offsets[i]:b.offsets[i + 1]] = sub_solution(p)
+    outs = {}
+    for opt in (1, 2, 4):
+        for op in ("vi", "eval", "adjoint"):
+            b.set_round_form(op, opt)
+        assert b.round_forms() == {"vi": opt, "eval": opt, "adjoint": opt}
+        V = lb.clone()
+        b.vi_solve(V, tol=1e-6)
+        pi, _ = b.policy_extract(V, want_gap=False)
+        Vp, _, _, _ = b.policy_eval(pi, V.double(), tol=1e-11)
+        grads, objs, w, _, _ = b.vi_adjoint(pi, Vp, [p.J for p in insts], tol=1e-10)
+        outs[opt] = (V.cpu().numpy().view(np.uint32), Vp.cpu().numpy().view(np.uint64),
+                     w.cpu().numpy().view(np.uint32), np.concatenate([np.array(g) for g in grads]))
+    for opt in (2, 4):
+        for x, y in zip(outs[1], outs[opt]):
+            assert np.array_equal(x, y), opt
+    for op in ("vi", "eval", "adjoint"):
+        b.set_round_form(op, 0)
+    rec = b.autotune(trials=3)
+    print(f"{case}: tuned {rec}", flush=True)
+    for op, (opt, us) in rec.items():
+        assert opt in (1, 2, 4) and us > 0, (op, opt, us)
+    other = mdpvi.Batch(insts)
+    assert other.round_forms() == {op: rec[op][0] for op in rec}
+    with pytest.raises(mdpvi.MdpviError):
+        other.set_round_form("vi", 3)
