@@ -72,6 +72,7 @@ def batched_vs_per_instance(mdpvi, n: int, tol: float) -> dict:
     import workloads as W
     insts = W.batch(n, seed=3)
     b = mdpvi.Batch(insts)
+    tuned = b.autotune(trials=3)               # untimed: round-kernel tile sizes for these shapes
     V = torch.zeros(b.num_states, device="cuda")
     b.vi_solve(V, tol=tol)                     # warm-up (first-use allocations)
     V.zero_()
@@ -95,7 +96,9 @@ def batched_vs_per_instance(mdpvi, n: int, tol: float) -> dict:
     return {"instances": n, "states": b.num_states, "tol": tol,
             "batched_seconds": t_batch, "batched_backups_per_s": st["backups"] / t_batch,
             "per_instance_seconds": t_single, "per_instance_backups_per_s": backups_single / t_single,
-            "speedup": t_single / t_batch, "max_sweeps": max(its)}
+            "speedup": t_single / t_batch, "max_sweeps": max(its),
+            "round_kernel_occupancies_per_thread": b.round_forms(),
+            "autotuned_us_per_round": {k: v[1] for k, v in tuned.items()}}
 
 
 def tolerance_runs(mdp, V, tol: float, t_abs: float, sweeps_abs) -> dict:
@@ -262,32 +265,47 @@ def gradient_workloads(mdpvi, n_batch: int, tol: float) -> dict:
 
     insts = W.batch(512, seed=3)[:n_batch]
     b = mdpvi.Batch(insts)
+    b_tuned = b.autotune(trials=3)     # untimed: round-kernel tile sizes for these shapes
     N = b.num_states
     lb = torch.zeros(N, device="cuda")
     for i, p in enumerate(insts):
         lb[b.offsets[i]:b.offsets[i + 1]] = _sub_solution(p)
 
     def batched():
+        stages = {}
         V = lb.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        t = t0
+
+        def mark(name):
+            nonlocal t
+            torch.cuda.synchronize()
+            now = time.perf_counter()
+            stages[name] = stages.get(name, 0.0) + now - t
+            t = now
+
         b.vi_solve(V, tol=tol)
+        mark("value_iteration")
         pi, _ = b.policy_extract(V, want_gap=False)
         Vp = V.double()
-        for _ in range(8):
+        rounds = 0
+        for rounds in range(1, 9):
             b.policy_eval(pi, Vp, tol=1e-12)
             pi2, _ = b.policy_extract(Vp, want_gap=False)
             if torch.equal(pi2, pi):
                 break
             pi = pi2
+        mark("evaluation_and_improvement")
         grads, objs, _, _, _ = b.vi_adjoint(pi, Vp, [p.J for p in insts], tol=1e-10)
+        mark("adjoint_gradient")
         pig = b.policy_greedy("least_loaded")
         Vg, _, _, _ = b.policy_eval(pig, tol=1e-12)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0, objs, Vg
+        mark("greedy_evaluation")
+        return time.perf_counter() - t0, objs, Vg, stages, rounds
 
     batched()
-    t_batch, objs, Vg = batched()
+    t_batch, objs, Vg, stages, pi_rounds = batched()
     Vg_h = Vg.cpu().numpy()
     gaps = []
     for i, p in enumerate(insts):
@@ -303,6 +321,9 @@ def gradient_workloads(mdpvi, n_batch: int, tol: float) -> dict:
                        "dJ_dtheta": list(g)},
             "batched": {"instances": n_batch, "states": N, "seconds": t_batch,
                         "gradients_per_s": n_batch / t_batch,
+                        "stage_seconds": stages, "evaluation_rounds": pi_rounds,
+                        "round_kernel_occupancies_per_thread": b.round_forms(),
+                        "autotuned_us_per_round": {k: v[1] for k, v in b_tuned.items()},
                         "mean_J_opt_minus_J_greedy": float(np.mean(gaps)),
                         "min_J_opt_minus_J_greedy": float(np.min(gaps))}}
 
