@@ -664,6 +664,8 @@ struct mdpvi_batch {
   mdpvi::BatchCtl* d_ctl = nullptr;
   int* d_remaining = nullptr;       // [0] unfinished instances, [1] active tiles after a compaction
   mdpvi::Tile* d_act[2] = {nullptr, nullptr};   // active-tile lists of the round loops
+  double* d_A[2] = {nullptr, nullptr};          // FP64 arrival terms of the round-form instances (VI)
+  int64_t a_total = 0;                          // their length: sum of n_occ + 1
   mdpvi::BatchOut* d_out = nullptr;
   float* W = nullptr;               // ping-pong partner of the concatenated values
   int* h_remaining = nullptr;       // pinned
@@ -1421,10 +1423,16 @@ int ensure_batch_device(mdpvi_batch* b) {
   for (int i = 0; i < n; ++i) {
     inst[i].M = b->models[i];
     inst[i].offset = b->offsets[i];
+    inst[i].aoff = -1;
     inst[i].lds = 0;
     inst[i].ctl = -1;
   }
   for (int32_t i : b->lds_list) inst[i].lds = 1;
+  b->a_total = 0;
+  for (int32_t i : b->round_list) {
+    inst[i].aoff = b->a_total;
+    b->a_total += b->models[i].n_occ + 1;
+  }
   for (int i = 0; i < n; ++i) inst[i].ctl = i;
   n_ctl = n;
   auto dalloc = [&](void** p, size_t bytes) -> int {
@@ -1455,6 +1463,8 @@ int ensure_batch_device(mdpvi_batch* b) {
     if ((rc = dalloc(reinterpret_cast<void**>(&b->d_act[a]),
                      std::max<size_t>(b->rtiles_all[0].size(), 1) * sizeof(mdpvi::Tile))))
       return rc;
+  for (int a = 0; a < 2; ++a)
+    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_A[a]), b->a_total * sizeof(double)))) return rc;
   for (int oi = 0; oi < 3; ++oi) {
     if ((rc = dalloc(reinterpret_cast<void**>(&b->d_rtiles[oi]), b->rtiles[oi].size() * sizeof(mdpvi::Tile))))
       return rc;
@@ -1598,6 +1608,8 @@ void mdp_free_batch(mdpvi_batch_t b) {
   (void)hipFree(b->d_remaining);
   (void)hipFree(b->d_act[0]);
   (void)hipFree(b->d_act[1]);
+  (void)hipFree(b->d_A[0]);
+  (void)hipFree(b->d_A[1]);
   for (int oi = 0; oi < 3; ++oi) {
     (void)hipFree(b->d_rtiles[oi]);
     (void)hipFree(b->d_rtiles_all[oi]);
@@ -1656,11 +1668,12 @@ int vi_solve_batch(mdpvi_batch_t b, float* V, double tol, int64_t max_iter, void
     const int opt = batch_opt(b, 0);
     const mdpvi::Tile* tiles = b->d_rtiles[opt_index(opt)];
     int nt = static_cast<int>(b->rtiles[opt_index(opt)].size()), cur = 0;
+    HIP_TRY(mdpvi::launch_batch_arrival_init(b->d_inst, tiles, nt, V, b->d_A[0], b->d_A[1], opt, s));
     while (issued < max_iter) {
       const int64_t m = std::min<int64_t>(chunk, max_iter - issued);
       for (int64_t k = 0; k < m; ++k)
         HIP_TRY(mdpvi::launch_batch_round(b->d_inst, tiles, nt, b->rnd_maxK, b->rnd_maxJ, V, b->W, b->d_ctl,
-                                          b->d_remaining, issued + k, tol, opt, s));
+                                          b->d_remaining, issued + k, tol, opt, b->d_A[0], b->d_A[1], s));
       issued += m;
       // drop the tiles of instances that have stopped from the next chunk
       HIP_TRY(mdpvi::launch_batch_compact(tiles, nt, b->d_ctl, b->d_act[cur], b->d_remaining + 1, s));
@@ -1954,10 +1967,11 @@ int batch_autotune(mdpvi_batch_t b, int32_t trials, void* hip_stream, int32_t* o
         const int o = 1 << oi;
         const mdpvi::Tile* tiles = vi ? b->d_rtiles[oi] : b->d_rtiles_all[oi];
         const int nt = static_cast<int>(vi ? b->rtiles[oi].size() : b->rtiles_all[oi].size());
+        if (vi) HIP_TRY(mdpvi::launch_batch_arrival_init(b->d_inst, tiles, nt, v32, b->d_A[0], b->d_A[1], o, s));
         auto round = [&]() -> hipError_t {
           if (op == 0)
             return mdpvi::launch_batch_round(b->d_inst, tiles, nt, b->rnd_maxK, b->rnd_maxJ, v32, b->W, b->d_ctl,
-                                             b->d_remaining, 0, 1.0, o, s);
+                                             b->d_remaining, 0, 1.0, o, b->d_A[0], b->d_A[1], s);
           if (op == 1)
             return mdpvi::launch_batch_eval_round(b->d_inst, tiles, nt, b->maxK, b->maxJ, pol, v64, w64, b->d_ctl,
                                                   b->d_remaining, 0, 1.0, o, s);

@@ -89,31 +89,40 @@ __global__ __launch_bounds__(kLdsBlock) void batch_lds_vi_kernel(const BatchInst
 // KM, JM), run_exact the exact-shape one (K hosts and J classes known at
 // compile time, every load issued before the first use), which gives the
 // same bits; exact_ok tells whether an instance meets run_exact's terms.
+// Value iteration's exact backup reads the FP64 arrival terms of the
+// previous round from the instance's side array (ain: n_occ entries and a
+// -inf entry for placements without room) and writes this round's (aout).
 struct VIOp {
   using T = float;
   static constexpr ResKind RK = ResKind::kMax;
+  static constexpr bool kSideArrays = true;
   template <int KM, int JM>
   __device__ static double run(const Model& M, const uint8_t*, const T* in, T* out, uint32_t o) {
     return backup_occupancy<KM, JM, uint32_t>(M, in, out, o);
   }
-  __device__ static bool exact_ok(const Model& M) {
-    return M.n_states < (int64_t{1} << 29) && M.J <= 3 && M.n_sizes == M.J;
+  __device__ static bool exact_ok(const BatchInst& I) {
+    const Model& M = I.M;
+    return I.aoff >= 0 && M.n_states < (int64_t{1} << 29) && M.J <= 3 && M.n_sizes == M.J;
   }
   template <int K, int J>
-  __device__ static double run_exact(const Model& M, const uint8_t*, const T* in, T* out, uint32_t o) {
-    return backup_exact<K, J>(M, make_view(in, static_cast<uint32_t>(M.n_states) * 4u), out, o);
+  __device__ static double run_exact(const Model& M, const uint8_t*, const T* in, T* out, const double* ain,
+                                     double* aout, uint32_t o) {
+    return backup_arrival<K, J>(M, make_view(in, static_cast<uint32_t>(M.n_states) * 4u),
+                                make_view(ain, static_cast<uint32_t>(M.n_occ + 1) * 8u), out, aout, o);
   }
 };
 struct EvalOp {
   using T = double;
   static constexpr ResKind RK = ResKind::kMax;
+  static constexpr bool kSideArrays = false;
   template <int KM, int JM>
   __device__ static double run(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
     return eval_occupancy<KM, JM, uint32_t>(M, pi, in, out, o);
   }
-  __device__ static bool exact_ok(const Model& M) { return M.n_states < (int64_t{1} << 28) && M.J <= 3; }
+  __device__ static bool exact_ok(const BatchInst& I) { return I.M.n_states < (int64_t{1} << 28) && I.M.J <= 3; }
   template <int K, int J>
-  __device__ static double run_exact(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
+  __device__ static double run_exact(const Model& M, const uint8_t* pi, const T* in, T* out, const double*,
+                                     double*, uint32_t o) {
     return eval_exact<K, J>(M, make_view(pi, static_cast<uint32_t>(M.n_states)),
                             make_view(in, static_cast<uint32_t>(M.n_states) * 8u), out, o);
   }
@@ -121,13 +130,15 @@ struct EvalOp {
 struct AdjOp {
   using T = float;
   static constexpr ResKind RK = ResKind::kSum;
+  static constexpr bool kSideArrays = false;
   template <int KM, int JM>
   __device__ static double run(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
     return adjoint_occupancy<KM, JM, uint32_t>(M, pi, in, out, o);
   }
-  __device__ static bool exact_ok(const Model& M) { return M.J <= 3; }
+  __device__ static bool exact_ok(const BatchInst& I) { return I.M.J <= 3; }
   template <int K, int J>
-  __device__ static double run_exact(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
+  __device__ static double run_exact(const Model& M, const uint8_t* pi, const T* in, T* out, const double*,
+                                     double*, uint32_t o) {
     return adjoint_occupancy_exact<K, J>(M, pi, in, out, o);
   }
 };
@@ -177,12 +188,12 @@ __device__ __forceinline__ bool inst_stopped(BatchCtl* c, long long j, double to
 template <class Op, int K, int J>
 __device__ __forceinline__ double round_tile_exact(const Model& M, const uint8_t* p,
                                                    const typename Op::T* Vin, typename Op::T* Vout,
-                                                   uint32_t first, int opt) {
+                                                   const double* Ain, double* Aout, uint32_t first, int opt) {
   double acc = 0.0;
   for (int k = 0; k < opt; ++k) {
     const uint32_t o = first + threadIdx.x + k * kBlock;
     if (o < static_cast<uint32_t>(M.n_occ)) {
-      const double d = Op::template run_exact<K, J>(M, p, Vin, Vout, o);
+      const double d = Op::template run_exact<K, J>(M, p, Vin, Vout, Ain, Aout, o);
       if constexpr (Op::RK == ResKind::kMax) acc = (d > acc || d != d) ? d : acc;
       else acc += d;
     }
@@ -203,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
                                                               const uint8_t* __restrict__ pi,
                                                               BatchCtl* __restrict__ ctl,
                                                               int* remaining, long long j, double tol,
-                                                              int opt) {
+                                                              int opt, double* A0, double* A1) {
   using T = typename Op::T;
   const Tile tile = tiles[blockIdx.x];
   const BatchInst& I = insts[tile.inst];
@@ -216,11 +227,13 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
   double acc = 0.0;
   bool done = false;
   if constexpr (EXACT) {
-    if (Op::exact_ok(M)) {
+    if (Op::exact_ok(I) && (!Op::kSideArrays || A0 != nullptr)) {
       done = true;
+      const double* Ain = A0 ? ((j & 1) ? A1 : A0) + I.aoff : nullptr;
+      double* Aout = A0 ? ((j & 1) ? A0 : A1) + I.aoff : nullptr;
       switch (M.K * 4 + M.J) {
 #define MDPVI_ROUND_CASE(K_, J_) \
-  case K_ * 4 + J_: acc = round_tile_exact<Op, K_, J_>(M, p, Vin, Vout, tile.first, opt); break;
+  case K_ * 4 + J_: acc = round_tile_exact<Op, K_, J_>(M, p, Vin, Vout, Ain, Aout, tile.first, opt); break;
         MDPVI_ROUND_CASE(1, 1) MDPVI_ROUND_CASE(1, 2) MDPVI_ROUND_CASE(1, 3)
         MDPVI_ROUND_CASE(2, 1) MDPVI_ROUND_CASE(2, 2) MDPVI_ROUND_CASE(2, 3)
         MDPVI_ROUND_CASE(3, 1) MDPVI_ROUND_CASE(3, 2) MDPVI_ROUND_CASE(3, 3)
@@ -299,6 +312,33 @@ __global__ void batch_round_finish_kernel(const BatchInst* __restrict__ insts,
     }
     out[i].iterations = fin;
     out[i].residual = r;
+  }
+}
+
+// Arrival terms A(o) = sum_e lambda_e/Lam V(o, e) of the initial iterate
+// (backup_arrival's FMA chain) into A0 for the instances with side arrays,
+// and the -inf entry A[n_occ] into both arrays.
+__global__ __launch_bounds__(kBlock) void batch_arrival_init_kernel(const BatchInst* __restrict__ insts,
+                                                                     const Tile* __restrict__ tiles,
+                                                                     const float* __restrict__ V,
+                                                                     double* __restrict__ A0,
+                                                                     double* __restrict__ A1, int opt) {
+  const Tile tile = tiles[blockIdx.x];
+  const BatchInst& I = insts[tile.inst];
+  if (I.aoff < 0) return;
+  const Model& M = I.M;
+  const uint64_t nocc = static_cast<uint64_t>(M.n_occ);
+  if (tile.first == 0 && threadIdx.x == 0) {
+    A0[I.aoff + nocc] = -INFINITY;
+    A1[I.aoff + nocc] = -INFINITY;
+  }
+  for (int k = 0; k < opt; ++k) {
+    const uint64_t o = tile.first + threadIdx.x + static_cast<uint64_t>(k) * kBlock;
+    if (o >= nocc) break;
+    double a = 0.0;
+    for (int e = 0; e < M.J; ++e)
+      a = fma(M.p[e], static_cast<double>(V[I.offset + o + static_cast<uint64_t>(e) * nocc]), a);
+    A0[I.aoff + o] = a;
   }
 }
 
@@ -503,6 +543,13 @@ hipError_t launch_batch_lds_vi(const BatchInst* insts, const int32_t* list, int 
   });
 }
 
+hipError_t launch_batch_arrival_init(const BatchInst* insts, const Tile* tiles, int n_tiles, const float* V,
+                                     double* A0, double* A1, int opt, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_arrival_init_kernel, dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles, V, A0, A1, opt);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_compact(const Tile* in, int n_in, const BatchCtl* ctl, Tile* out, int* n_out,
                                 hipStream_t s) {
   hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(1), 0, s, n_out);
@@ -522,38 +569,41 @@ template <class Op>
 static hipError_t launch_round_t(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                  int maxJ, typename Op::T* V, typename Op::T* W, const uint8_t* pi,
                                  BatchCtl* ctl, int* remaining, long long j, double tol, int opt,
-                                 hipStream_t s) {
+                                 double* A0, double* A1, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   if (opt < 1 || opt > kOccPerThread) return hipErrorInvalidValue;
   if (maxK <= kBatchExactK && maxJ <= 3) {
     hipLaunchKernelGGL((batch_round_kernel<Op, 8, 4, true>), dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles,
-                       V, W, pi, ctl, remaining, j, tol, opt);
+                       V, W, pi, ctl, remaining, j, tol, opt, A0, A1);
     return hipGetLastError();
   }
   return dispatch_kj_b(maxK, maxJ, [&](auto km, auto jm) {
     constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
     hipLaunchKernelGGL((batch_round_kernel<Op, KM, JM, false>), dim3(n_tiles), dim3(kBlock), 0, s, insts,
-                       tiles, V, W, pi, ctl, remaining, j, tol, opt);
+                       tiles, V, W, pi, ctl, remaining, j, tol, opt, A0, A1);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                               int maxJ, float* V, float* W, BatchCtl* ctl, int* remaining,
-                              long long j, double tol, int opt, hipStream_t s) {
-  return launch_round_t<VIOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, nullptr, ctl, remaining, j, tol, opt, s);
+                              long long j, double tol, int opt, double* A0, double* A1, hipStream_t s) {
+  return launch_round_t<VIOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, nullptr, ctl, remaining, j, tol, opt,
+                              A0, A1, s);
 }
 
 hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                    int maxJ, const uint8_t* pi, double* V, double* W, BatchCtl* ctl,
                                    int* remaining, long long j, double tol, int opt, hipStream_t s) {
-  return launch_round_t<EvalOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, pi, ctl, remaining, j, tol, opt, s);
+  return launch_round_t<EvalOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, pi, ctl, remaining, j, tol, opt,
+                                nullptr, nullptr, s);
 }
 
 hipError_t launch_batch_adjoint_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                       int maxJ, const uint8_t* pi, float* w, float* W, BatchCtl* ctl,
                                       int* remaining, long long j, double tol, int opt, hipStream_t s) {
-  return launch_round_t<AdjOp>(insts, tiles, n_tiles, maxK, maxJ, w, W, pi, ctl, remaining, j, tol, opt, s);
+  return launch_round_t<AdjOp>(insts, tiles, n_tiles, maxK, maxJ, w, W, pi, ctl, remaining, j, tol, opt,
+                               nullptr, nullptr, s);
 }
 
 template <typename T, ResKind RK>

@@ -12,6 +12,8 @@ constexpr size_t kLdsBudget = 160 * 1024 - 1024;  // dynamic LDS per workgroup
 struct BatchInst {
   Model M;
   int64_t offset;   // first state of this instance in the concatenated arrays
+  int64_t aoff;     // first entry of its arrival terms (n_occ + 1 doubles) in the
+                    // value-iteration side arrays; -1 when it has none
   int32_t lds;      // 1: solved LDS-resident by one workgroup
   int32_t ctl;      // index of its round-form control block (-1 if none)
 };

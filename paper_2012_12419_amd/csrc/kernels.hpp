@@ -128,9 +128,16 @@ hipError_t launch_batch_ctl_init(BatchCtl* ctl, const int32_t* list, int n_list,
                                  int* flags, int n_flags, hipStream_t s);
 // One round of value iteration, FP64 evaluation or the adjoint over the
 // given tiles (kBlock * opt occupancies each, opt in 1..kOccPerThread).
+// Value iteration's round reads and writes the FP64 arrival terms of the
+// instances with side arrays in A0/A1 (ping-pong like V/W; nullptr: every
+// instance takes the backup without them).
 hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                               int maxJ, float* V, float* W, BatchCtl* ctl, int* remaining,
-                              long long j, double tol, int opt, hipStream_t s);
+                              long long j, double tol, int opt, double* A0, double* A1, hipStream_t s);
+// The arrival terms of V (the initial iterate) into A0, the -inf entries
+// into A0 and A1, for the instances of the tiles that have side arrays.
+hipError_t launch_batch_arrival_init(const BatchInst* insts, const Tile* tiles, int n_tiles, const float* V,
+                                     double* A0, double* A1, int opt, hipStream_t s);
 hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                    int maxJ, const uint8_t* pi, double* V, double* W, BatchCtl* ctl,
                                    int* remaining, long long j, double tol, int opt, hipStream_t s);
