@@ -333,6 +333,26 @@ int policy_eval_batch(mdpvi_batch_t b, const uint8_t *pi, double *V, double tol,
                       int64_t max_iter, void *hip_stream, mdpvi_stats *st,
                       int64_t *iterations, double *residuals);
 
+/* Policy iteration of every instance (as policy_iteration, per instance):
+ * repeat { FP64 evaluation of the instances still running (round form, to
+ * eval_tol, at most eval_max_iter sweeps, each from its previous values);
+ * in-place improvement of those instances with tolerance improve_tol } and
+ * an instance stops at the first improvement that changes none of its
+ * actions, so V holds the value of its final policy.  pi (device uint8[N]):
+ * in the starting policies (feasible), out the final ones; V (device
+ * double[N]): in the starting iterates, out V_pi.  rounds (host int64[n],
+ * nullable): evaluations per instance.  st: evaluation sweeps summed over
+ * rounds (iterations = sum over rounds of the longest instance's sweeps),
+ * largest residual and bound, host wall seconds.  Synchronous.  Errors:
+ * MDPVI_EINVAL (NULL pointer, eval_tol <= 0, improve_tol < 0 or not finite,
+ * eval_max_iter or max_rounds < 1, an infeasible action); MDPVI_ENOCONV
+ * (an evaluation reached eval_max_iter, or instances still change after
+ * max_rounds; outputs hold the last round's); MDPVI_ENAN, MDPVI_EDEVICE,
+ * MDPVI_ENOMEM.                                                            */
+int policy_iteration_batch(mdpvi_batch_t b, uint8_t *pi, double *V, double eval_tol,
+                           int64_t eval_max_iter, double improve_tol, int64_t max_rounds,
+                           void *hip_stream, mdpvi_stats *st, int64_t *rounds);
+
 /* Batched vi_adjoint.  w: device float[total] in w^0, out the adjoint weights.
  * grad: host array of sum_i (2 J_i + 2) doubles, instance i's gradient
  * (lambda_1..J_i, mu, nu, r_1..J_i) at offset sum_{k<i} (2 J_k + 2);

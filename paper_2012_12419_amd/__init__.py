@@ -95,6 +95,8 @@ SIGNATURES = {
     "vi_adjoint_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_c_double),
                                         ctypes.POINTER(_c_double), _c_double, _c_int64, _vp,
                                         ctypes.POINTER(Stats), ctypes.POINTER(_c_int64)]),
+    "policy_iteration_batch": (ctypes.c_int, [_vp, _vp, _vp, _c_double, _c_int64, _c_double, _c_int64, _vp,
+                                              ctypes.POINTER(Stats), ctypes.POINTER(_c_int64)]),
     "batch_set_round_form": (ctypes.c_int, [_vp, _c_int32, _c_int32]),
     "batch_round_forms": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int32)]),
     "batch_autotune": (ctypes.c_int, [_vp, _c_int32, _vp, ctypes.POINTER(_c_int32),
@@ -469,6 +471,20 @@ class Batch:
                                         _dev_tensor(V, torch.float64, n, "V"), float(tol), int(max_iter),
                                         _stream_ptr(stream), ctypes.byref(st), its, res), st)
         return V, st.as_dict(), list(its), list(res)
+
+    def policy_iteration(self, pi, V, eval_tol: float = 1e-12, eval_max_iter: int = 10_000_000,
+                         improve_tol: float = 1e-9, max_rounds: int = 50, stream=None):
+        """Per-instance policy iteration in place on pi (uint8) and V (FP64);
+        returns (stats, evaluations per instance)."""
+        import torch
+        n = self.num_states
+        st = Stats()
+        rounds = (_c_int64 * self.n)()
+        _check(load().policy_iteration_batch(self._h, _dev_tensor(pi, torch.uint8, n, "pi"),
+                                             _dev_tensor(V, torch.float64, n, "V"), float(eval_tol),
+                                             int(eval_max_iter), float(improve_tol), int(max_rounds),
+                                             _stream_ptr(stream), ctypes.byref(st), rounds), st)
+        return st.as_dict(), list(rounds)
 
     def vi_adjoint(self, pi, V_pi, J_sizes, w=None, tol: float = 1e-10, max_iter: int = 10_000_000,
                    stream=None):

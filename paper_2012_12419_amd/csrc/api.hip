@@ -665,6 +665,9 @@ struct mdpvi_batch {
   int* d_remaining = nullptr;       // [0] unfinished instances, [1] active tiles after a compaction
   mdpvi::Tile* d_act[2] = {nullptr, nullptr};   // active-tile lists of the round loops
   double* d_A[2] = {nullptr, nullptr};          // FP64 arrival terms of the round-form instances (VI)
+  int* d_active[2] = {nullptr, nullptr};        // per-instance flags of batched policy iteration
+  int* h_active = nullptr;                      // pinned
+  uint8_t* d_pbuf = nullptr;                    // policy scratch (round check), on first use
   int64_t a_total = 0;                          // their length: sum of n_occ + 1
   mdpvi::BatchOut* d_out = nullptr;
   float* W = nullptr;               // ping-pong partner of the concatenated values
@@ -1463,8 +1466,15 @@ int ensure_batch_device(mdpvi_batch* b) {
     if ((rc = dalloc(reinterpret_cast<void**>(&b->d_act[a]),
                      std::max<size_t>(b->rtiles_all[0].size(), 1) * sizeof(mdpvi::Tile))))
       return rc;
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 2; ++a) {
     if ((rc = dalloc(reinterpret_cast<void**>(&b->d_A[a]), b->a_total * sizeof(double)))) return rc;
+    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_active[a]), n * sizeof(int)))) return rc;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_active), std::max(n, 1) * sizeof(int), hipHostMallocDefault) !=
+      hipSuccess) {
+    b->h_active = nullptr;
+    return fail(MDPVI_ENOMEM, "hipHostMalloc of the batch flags failed");
+  }
   for (int oi = 0; oi < 3; ++oi) {
     if ((rc = dalloc(reinterpret_cast<void**>(&b->d_rtiles[oi]), b->rtiles[oi].size() * sizeof(mdpvi::Tile))))
       return rc;
@@ -1610,6 +1620,9 @@ void mdp_free_batch(mdpvi_batch_t b) {
   (void)hipFree(b->d_act[1]);
   (void)hipFree(b->d_A[0]);
   (void)hipFree(b->d_A[1]);
+  (void)hipFree(b->d_active[0]);
+  (void)hipFree(b->d_active[1]);
+  if (b->h_active) (void)hipHostFree(b->h_active);
   for (int oi = 0; oi < 3; ++oi) {
     (void)hipFree(b->d_rtiles[oi]);
     (void)hipFree(b->d_rtiles_all[oi]);
@@ -1750,16 +1763,29 @@ int batch_check_policy(mdpvi_batch* b, const uint8_t* pi, hipStream_t s, int* ba
 // Round-form loop over every instance: `round(j, tiles, n)` enqueues round j
 // over the n tiles of the instances still running, `finish(issued)`
 // writes back odd finals and the per-instance outputs.  Fills stats from them.
+// With `active` (device int[n], nullable), only the instances with
+// active[i] != 0 (n_active of them) are swept; the others keep their values
+// and report 0 sweeps.
 template <typename Round, typename Finish>
 int batch_all_rounds(mdpvi_batch* b, int opt, double tol, int64_t max_iter, hipStream_t s, mdpvi_stats* st,
                      int64_t* iterations, double* residuals, double bytes_per_state, Round round,
-                     Finish finish) {
-  HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_all, b->n, b->d_remaining, b->d_flags, 0, s));
-  HIP_TRY(hipEventRecord(b->ev0, s));
+                     Finish finish, const int* active = nullptr, int n_active = 0) {
   int64_t issued = 0, chunk = 8;
   const mdpvi::Tile* tiles = b->d_rtiles_all[opt_index(opt)];
   int nt = static_cast<int>(b->rtiles_all[opt_index(opt)].size()), cur = 0;
-  while (issued < max_iter) {
+  if (active) {
+    HIP_TRY(mdpvi::launch_batch_ctl_activate(b->d_ctl, active, b->n, b->d_remaining, n_active, s));
+    HIP_TRY(mdpvi::launch_batch_compact(tiles, nt, b->d_ctl, b->d_act[cur], b->d_remaining + 1, s));
+    HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    tiles = b->d_act[cur];
+    nt = b->h_remaining[1];
+    cur ^= 1;
+  } else {
+    HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_all, b->n, b->d_remaining, b->d_flags, 0, s));
+  }
+  HIP_TRY(hipEventRecord(b->ev0, s));
+  while (issued < max_iter && nt > 0) {
     const int64_t m = std::min<int64_t>(chunk, max_iter - issued);
     for (int64_t k = 0; k < m; ++k) HIP_TRY(round(issued + k, tiles, nt));
     issued += m;
@@ -1874,6 +1900,79 @@ int policy_eval_batch(mdpvi_batch_t b, const uint8_t* pi, double* V, double tol,
       [&](int64_t issued) {
         return mdpvi::launch_batch_eval_finish(b->d_inst, b->d_all, b->n, V, W, b->d_ctl, issued, b->d_out, s);
       });
+}
+
+int policy_iteration_batch(mdpvi_batch_t b, uint8_t* pi, double* V, double eval_tol, int64_t eval_max_iter,
+                           double improve_tol, int64_t max_rounds, void* hip_stream, mdpvi_stats* st,
+                           int64_t* rounds) {
+  if (!b || !pi || !V) return fail(MDPVI_EINVAL, "NULL batch, policy or value array");
+  if (!(improve_tol >= 0) || std::isinf(improve_tol))
+    return fail(MDPVI_EINVAL, "improve_tol=%g must be finite and >= 0", improve_tol);
+  if (max_rounds < 1) return fail(MDPVI_EINVAL, "max_rounds=%lld must be >= 1", (long long)max_rounds);
+  int rc = batch_args(b, eval_tol, eval_max_iter);
+  if (rc) return rc;
+  if (!b->W2) {
+    if (hipMalloc(&b->W2, std::max<int64_t>(b->offsets[b->n], 1) * sizeof(double)) != hipSuccess) {
+      b->W2 = nullptr;
+      return fail(MDPVI_ENOMEM, "hipMalloc of the FP64 batch scratch failed");
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int bad = -1;
+  if ((rc = batch_check_policy(b, pi, s, &bad))) return rc;
+  if (bad >= 0) return fail(MDPVI_EINVAL, "instance %d: policy has an infeasible action", bad);
+  double* W = static_cast<double*>(b->W2);
+  const int opt = batch_opt(b, 1);
+  const int n = b->n;
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<int64_t> rr(n, 0);
+  for (int i = 0; i < n; ++i) b->h_active[i] = 1;
+  HIP_TRY(hipMemcpyAsync(b->d_active[0], b->h_active, n * sizeof(int), hipMemcpyHostToDevice, s));
+  int n_active = n, a = 0;
+  int64_t r = 0;
+  mdpvi_stats tot{};
+  while (n_active > 0 && r < max_rounds) {
+    ++r;
+    for (int i = 0; i < n; ++i)
+      if (b->h_active[i]) ++rr[i];
+    mdpvi_stats e{};
+    rc = batch_all_rounds(
+        b, opt, eval_tol, eval_max_iter, s, &e, nullptr, nullptr, 17.0,
+        [&](long long j, const mdpvi::Tile* tiles, int nt) {
+          return mdpvi::launch_batch_eval_round(b->d_inst, tiles, nt, b->maxK, b->maxJ, pi, V, W, b->d_ctl,
+                                                b->d_remaining, j, eval_tol, opt, s);
+        },
+        [&](int64_t issued) {
+          return mdpvi::launch_batch_eval_finish(b->d_inst, b->d_all, n, V, W, b->d_ctl, issued, b->d_out, s);
+        },
+        b->d_active[a], n_active);
+    tot.iterations += e.iterations;
+    tot.residual_inf = std::max(tot.residual_inf, e.residual_inf);
+    tot.bound_inf = std::max(tot.bound_inf, e.bound_inf);
+    tot.backups += e.backups;
+    tot.bytes += e.bytes;
+    if (rc != MDPVI_OK) break;
+    // improvement of the instances just evaluated: an instance whose policy
+    // does not change is done (its V is the value of its final policy)
+    HIP_TRY(hipMemsetAsync(b->d_active[a ^ 1], 0, n * sizeof(int), s));
+    HIP_TRY(mdpvi::launch_batch_improve_active(b->d_inst, b->d_tiles_all, static_cast<int>(b->tiles_all.size()),
+                                               b->maxK, b->maxJ, V, pi, improve_tol, b->d_active[a],
+                                               b->d_active[a ^ 1], s));
+    HIP_TRY(hipMemcpyAsync(b->h_active, b->d_active[a ^ 1], n * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    a ^= 1;
+    n_active = 0;
+    for (int i = 0; i < n; ++i) n_active += b->h_active[i] ? 1 : 0;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  tot.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st) *st = tot;
+  if (rounds) std::memcpy(rounds, rr.data(), n * sizeof(int64_t));
+  if (rc != MDPVI_OK) return rc;
+  if (n_active > 0)
+    return fail(MDPVI_ENOCONV, "%d instances still change their policy after %lld rounds (max_rounds)", n_active,
+                (long long)r);
+  return MDPVI_OK;
 }
 
 int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t* pi, const double* V_pi, float* w, double* grad,

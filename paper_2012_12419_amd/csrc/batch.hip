@@ -304,7 +304,7 @@ __global__ void batch_round_finish_kernel(const BatchInst* __restrict__ insts,
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double r = 0.0;
-    for (int l = 0; l < kBatchLanes; ++l) {
+    for (int l = 0; l < kBatchLanes && fin > 0; ++l) {   // fin = 0: an instance that was not run
       const double v =
           __longlong_as_double(static_cast<long long>(load_agent(&c->res[(fin - 1) % kResSlots][l][0])));
       if constexpr (RK == ResKind::kMax) r = (v > r || v != v) ? v : r;
@@ -365,6 +365,42 @@ __global__ void batch_compact_kernel(const Tile* __restrict__ in, int n_in, cons
 }
 
 __global__ void batch_zero_kernel(int* p) { *p = 0; }
+
+// Control blocks of instances 0..n-1 for a round loop over the active ones
+// (active[i] != 0): done_iter -1 for those and 0 (already stopped, no sweep)
+// for the others, residual words cleared; *remaining = n_active.
+__global__ void batch_ctl_activate_kernel(BatchCtl* ctl, const int* __restrict__ active, int n,
+                                          int* remaining, int n_active) {
+  const int i = blockIdx.x;
+  if (i < n) {
+    BatchCtl* c = ctl + i;
+    if (threadIdx.x == 0) c->done_iter = active[i] ? -1 : 0;
+    for (int w = threadIdx.x; w < kResSlots * kBatchLanes; w += blockDim.x)
+      c->res[w / kBatchLanes][w % kBatchLanes][0] = 0ull;
+  }
+  if (i == 0 && threadIdx.x == 0) *remaining = n_active;
+}
+
+// Policy improvement (improve_occupancy, in place) of the tiles' instances
+// with active[inst] != 0; changed[inst] := 1 where some action changed
+// (changed must be cleared).  Tiles of kBlock * kOccPerThread occupancies.
+template <int KMAX, int JMAX>
+__global__ __launch_bounds__(kBlock) void batch_improve_kernel(const BatchInst* __restrict__ insts,
+                                                                const Tile* __restrict__ tiles,
+                                                                const double* __restrict__ V, uint8_t* pi,
+                                                                double tol, const int* __restrict__ active,
+                                                                int* __restrict__ changed) {
+  const Tile tile = tiles[blockIdx.x];
+  if (!active[tile.inst]) return;
+  const BatchInst& I = insts[tile.inst];
+  bool ch = false;
+  for (int k = 0; k < kOccPerThread; ++k) {
+    const uint32_t o = tile.first + threadIdx.x + k * kBlock;
+    if (o < static_cast<uint32_t>(I.M.n_occ))
+      ch |= improve_occupancy<KMAX, JMAX, uint32_t>(I.M, V + I.offset, pi + I.offset, pi + I.offset, tol, o);
+  }
+  if (__ballot(ch) != 0ull && threadIdx.x % kWave == 0) changed[tile.inst] = 1;
+}
 
 __global__ void batch_ctl_init_kernel(BatchCtl* ctl, const int32_t* __restrict__ list, int n_list,
                                       int* remaining, int* flags, int n_flags) {
@@ -548,6 +584,25 @@ hipError_t launch_batch_arrival_init(const BatchInst* insts, const Tile* tiles, 
   if (n_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(batch_arrival_init_kernel, dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles, V, A0, A1, opt);
   return hipGetLastError();
+}
+
+hipError_t launch_batch_ctl_activate(BatchCtl* ctl, const int* active, int n, int* remaining, int n_active,
+                                     hipStream_t s) {
+  hipLaunchKernelGGL(batch_ctl_activate_kernel, dim3(n > 0 ? n : 1), dim3(64), 0, s, ctl, active, n, remaining,
+                     n_active);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_improve_active(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK, int maxJ,
+                                       const double* V, uint8_t* pi, double tol, const int* active, int* changed,
+                                       hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  return dispatch_kj_b(maxK, maxJ, [&](auto km, auto jm) {
+    constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
+    hipLaunchKernelGGL((batch_improve_kernel<KM, JM>), dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles, V, pi,
+                       tol, active, changed);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_batch_compact(const Tile* in, int n_in, const BatchCtl* ctl, Tile* out, int* n_out,

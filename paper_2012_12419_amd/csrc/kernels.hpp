@@ -120,6 +120,16 @@ hipError_t launch_objective(const Model& M, const double* V, double* out, hipStr
 hipError_t launch_batch_lds_vi(const BatchInst* insts, const int32_t* list, int n_list, int maxK,
                                int maxJ, size_t lds_bytes, float* V, double tol, long long max_iter,
                                BatchOut* out, hipStream_t s);
+// Control blocks for a round loop over the instances with active[i] != 0
+// (the others count as stopped before their first sweep).
+hipError_t launch_batch_ctl_activate(BatchCtl* ctl, const int* active, int n, int* remaining, int n_active,
+                                     hipStream_t s);
+// In-place FP64 policy improvement (tolerance tol) of the tiles' instances
+// with active[inst] != 0 (tiles of kBlock * kOccPerThread occupancies);
+// changed[inst] := 1 where an action changed.
+hipError_t launch_batch_improve_active(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK, int maxJ,
+                                       const double* V, uint8_t* pi, double tol, const int* active, int* changed,
+                                       hipStream_t s);
 // The tiles of `in` whose instance has not stopped, into `out`; their count
 // into *n_out.
 hipError_t launch_batch_compact(const Tile* in, int n_in, const BatchCtl* ctl, Tile* out, int* n_out,

@@ -90,11 +90,13 @@ __device__ __forceinline__ void extract_occupancy(const Model& M, const T* __res
 
 // Policy improvement at occupancy o (all classes), Q formed in FP64 from V
 // as in extract_occupancy: the current action pi_in stays unless some action
-// beats its Q by more than tol; then the lowest-index argmax.
+// beats its Q by more than tol; then the lowest-index argmax.  Returns true
+// when some class's action changed.  pi_in may equal pi_out (each state
+// reads and writes only its own entry).
 template <int KMAX, int JMAX, typename Idx>
-__device__ __forceinline__ void improve_occupancy(const Model& M, const double* __restrict__ V,
-                                                  const uint8_t* __restrict__ pi_in, uint8_t* __restrict__ pi_out,
-                                                  double tol, Idx o) {
+__device__ __forceinline__ bool improve_occupancy(const Model& M, const double* __restrict__ V,
+                                                  const uint8_t* pi_in, uint8_t* pi_out, double tol, Idx o) {
+  bool changed = false;
   const Idx nocc = static_cast<Idx>(M.n_occ);
   int n[KMAX];
   decode<KMAX>(M, o, n);
@@ -130,9 +132,12 @@ __device__ __forceinline__ void improve_occupancy(const Model& M, const double* 
           }
         }
       }
-      pi_out[base] = static_cast<uint8_t>(q_cur >= best - tol ? cur : arg);
+      const int chosen = q_cur >= best - tol ? cur : arg;
+      changed |= chosen != cur;
+      pi_out[base] = static_cast<uint8_t>(chosen);
     }
   }
+  return changed;
 }
 
 // True if some class at occupancy o has an action that is not feasible.

@@ -1,7 +1,7 @@
 """GPU parity of the batched gradient and greedy-scoring pipeline.
 
 For every instance of a mixed batch: value iteration -> extraction -> FP64
-evaluation -> one FP64 improvement step -> adjoint gradient, and the
+policy iteration (per instance) -> adjoint gradient, and the
 least-loaded greedy policy with its FP64 value.  Checked against the FP64
 oracle instance by instance, and against the single-instance entry points
 bit for bit (same per-state arithmetic, same tile order in the reductions).
@@ -46,13 +46,10 @@ def _batch_pipeline(mdpvi, insts):
     _batch_pipeline.last_V = V
     pi, _ = b.policy_extract(V, want_gap=False)
     Vp = V.double()
-    # FP64 policy-iteration steps from the FP32 greedy policy until it is stable
-    for _ in range(8):
-        b.policy_eval(pi, Vp, tol=1e-12)
-        pi2, _ = b.policy_extract(Vp, want_gap=False)
-        if torch.equal(pi2, pi):
-            break
-        pi = pi2
+    # per-instance FP64 policy iteration from the FP32 greedy policy (an
+    # action changes only when another beats it by more than 1e-9)
+    _, rounds = b.policy_iteration(pi, Vp, eval_tol=1e-12, improve_tol=IMPROVE_TOL)
+    _batch_pipeline.rounds = rounds
     grads, objs, w, st, its = b.vi_adjoint(pi, Vp, [p.J for p in insts], tol=1e-11)
     pig = b.policy_greedy("least_loaded")
     Vg, _, _, _ = b.policy_eval(pig, tol=1e-12)
@@ -76,15 +73,32 @@ def test_batch_gradient_and_greedy_vs_oracle(mdpvi):
         V_o = vi.policy_eval(p, pi_o, tol=1e-13, g=g)
         mask = gap_mask(vi.q_table(p, star, g).max(axis=1), gap_o, star)
         assert np.array_equal(pi_h[sl][mask], pi_o[mask])
-        assert np.max(np.abs(Vp_h[sl] - V_o)) <= EVAL_REL * np.max(np.abs(V_o))
-        assert abs(objs[i] - vi.objective(p, V_o)) <= 1e-10 * max(1.0, abs(objs[i]))
-        g_o = grad.gradient_adjoint(p, pi_o, V=V_o)
+        # the GPU policy's value and gradient against the oracle's for that policy
+        V_pi = vi.policy_eval(p, pi_h[sl], tol=1e-13, g=g)
+        assert np.max(np.abs(Vp_h[sl] - V_pi)) <= EVAL_REL * np.max(np.abs(V_pi))
+        assert abs(objs[i] - vi.objective(p, V_pi)) <= 1e-10 * max(1.0, abs(objs[i]))
+        g_o = grad.gradient_adjoint(p, pi_h[sl], V=V_pi)
         assert np.max(np.abs(np.array(grads[i]) - g_o)) <= 1e-5 * np.max(np.abs(g_o))
+        _near_optimal(p, Vp_h[sl], V_o)
         pg_o = vi.greedy_policy(p, "least_loaded", g)
         assert np.array_equal(pig_h[sl], pg_o)
         Vg_o = vi.policy_eval(p, pg_o, tol=1e-13, g=g)
         assert np.max(np.abs(Vg_h[sl] - Vg_o)) <= EVAL_REL * np.max(np.abs(Vg_o))
         assert np.all(Vg_h[sl] <= Vp_h[sl] + 1e-9 * np.max(np.abs(V_o)))
+
+
+IMPROVE_TOL = 1e-9
+
+
+def _near_optimal(p, V, V_star, eval_tol=1e-12):
+    """A policy that no improvement by more than IMPROVE_TOL changes, with
+    values from an evaluation stopped at eval_tol (error bound b =
+    gamma/(1-gamma) eval_tol), is within (IMPROVE_TOL + 2 gamma b)/(1 - gamma)
+    of optimal."""
+    scale = np.max(np.abs(V_star))
+    b = p.gamma / (1 - p.gamma) * eval_tol
+    assert np.all(V <= V_star + EVAL_REL * scale)
+    assert np.all(V >= V_star - (IMPROVE_TOL + 2 * p.gamma * b) / (1 - p.gamma) - EVAL_REL * scale)
 
 
 def test_batch_gradient_equals_single_instance(mdpvi):
@@ -99,6 +113,33 @@ def test_batch_gradient_equals_single_instance(mdpvi):
         assert np.array_equal(w1.cpu().numpy().view(np.uint32), w[sl].cpu().numpy().view(np.uint32)), i
         V1, _ = mdp.policy_eval(pig[sl].contiguous(), tol=1e-12)
         assert np.array_equal(V1.cpu().numpy().view(np.uint64), Vg[sl].cpu().numpy().view(np.uint64)), i
+
+
+def test_batch_policy_iteration_equals_single_instance(mdpvi):
+    """Batched policy iteration stops each instance at its own first stable
+    improvement: per instance the same evaluations, final policy and value
+    bits as policy_iteration on that instance alone."""
+    import torch
+    insts = _instances()
+    b = mdpvi.Batch(insts)
+    V = torch.zeros(b.num_states, device="cuda")
+    for i, p in enumerate(insts):
+        V[b.offsets[i]:b.offsets[i + 1]] = sub_solution(p)
+    b.vi_solve(V, tol=1e-6)
+    pi0, _ = b.policy_extract(V, want_gap=False)
+    pi, Vp = pi0.clone(), V.double()
+    _, rounds = b.policy_iteration(pi, Vp, eval_tol=1e-12, improve_tol=IMPROVE_TOL)
+    print("rounds per instance", rounds, flush=True)
+    assert max(rounds) > 1
+    for i, p in enumerate(insts):
+        sl = slice(b.offsets[i], b.offsets[i + 1])
+        mdp = mdpvi.MDP.from_instance(p)
+        pi1 = pi0[sl].clone()
+        V1 = V[sl].double()
+        _, _, _, r1 = mdp.policy_iteration(pi1, V1, eval_tol=1e-12, improve_tol=IMPROVE_TOL)
+        assert r1 == rounds[i], (i, r1, rounds[i])
+        assert torch.equal(pi1, pi[sl]), i
+        assert np.array_equal(V1.cpu().numpy().view(np.uint64), Vp[sl].cpu().numpy().view(np.uint64)), i
 
 
 def _eval_residual(p, pi, V):
@@ -131,8 +172,10 @@ def test_batch_pipeline_first_256_of_sweep(mdpvi):
       its policy is greedy with respect to that value under the oracle's Q
       (so it is optimal); its adjoint weights satisfy the adjoint equation;
     * the instances of at most 30,000 states (190 of them) against the
-      oracle's full pipeline: policy on the parity gap mask, FP64 value,
-      objective, gradient, greedy policy and its value."""
+      oracle's full pipeline: policy on the parity gap mask of the oracle's
+      optimal policy; FP64 value, objective and gradient against the oracle's
+      for the GPU's policy, and the value within IMPROVE_TOL / (1 - gamma) of
+      the optimal one; greedy policy and its value."""
     import torch
 
     from tests.oracle_pool import batch_oracle
@@ -166,13 +209,14 @@ def test_batch_pipeline_first_256_of_sweep(mdpvi):
             print(f"instances 0..{i}: checks hold", flush=True)
     print(f"256 instances: single-instance bit identity and oracle properties hold; "
           f"oracle pipeline on {len(small)} instances", flush=True)
-    ref = batch_oracle(small, 512, 3)
+    ref = batch_oracle(small, 512, 3, policies={i: pi_h[b.offsets[i]:b.offsets[i + 1]] for i in small})
     for i in small:
         p, o = insts[i], ref[i]
         sl = slice(b.offsets[i], b.offsets[i + 1])
         assert np.array_equal(pi_h[sl][o["mask"]], o["pi"][o["mask"]]), i
-        assert np.max(np.abs(Vp_h[sl] - o["V"])) <= EVAL_REL * np.max(np.abs(o["V"])), i
-        assert abs(objs[i] - o["J"]) <= 1e-10 * max(1.0, abs(o["J"])), i
-        assert np.max(np.abs(np.array(grads[i]) - o["grad"])) <= 1e-5 * np.max(np.abs(o["grad"])), i
+        assert np.max(np.abs(Vp_h[sl] - o["V_pi"])) <= EVAL_REL * np.max(np.abs(o["V_pi"])), i
+        assert abs(objs[i] - o["J_pi"]) <= 1e-10 * max(1.0, abs(o["J_pi"])), i
+        assert np.max(np.abs(np.array(grads[i]) - o["grad_pi"])) <= 1e-5 * np.max(np.abs(o["grad_pi"])), i
+        _near_optimal(p, Vp_h[sl], o["V"])
         assert np.array_equal(pig_h[sl], o["greedy"]), i
         assert np.max(np.abs(Vg_h[sl] - o["V_greedy"])) <= EVAL_REL * np.max(np.abs(o["V_greedy"])), i
