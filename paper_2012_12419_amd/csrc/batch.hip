@@ -36,16 +36,11 @@ namespace mdpvi {
 
 // ---------------------------------------------------------------- LDS form
 
+// The LDS-resident solve of one instance by the calling workgroup, with the
+// backup of bounds KMAX, JMAX (KMAX = K and JMAX = J: exact loops).
 template <int KMAX, int JMAX>
-__global__ __launch_bounds__(kLdsBlock) void batch_lds_vi_kernel(const BatchInst* __restrict__ insts,
-                                                                  const int32_t* __restrict__ list,
-                                                                  float* __restrict__ V, double tol,
-                                                                  long long max_iter,
-                                                                  BatchOut* __restrict__ out) {
-  extern __shared__ float lds[];
-  __shared__ double part[kLdsBlock / kWave];
-  const int i = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
-  const BatchInst& I = insts[i];
+__device__ __forceinline__ void lds_solve(const BatchInst& I, int i, float* lds, double* part, float* V,
+                                          double tol, long long max_iter, BatchOut* out) {
   const Model& M = I.M;
   const uint32_t N = static_cast<uint32_t>(M.n_states);
   const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
@@ -80,6 +75,33 @@ __global__ __launch_bounds__(kLdsBlock) void batch_lds_vi_kernel(const BatchInst
   if (threadIdx.x == 0) {
     out[i].iterations = it;
     out[i].residual = res;
+  }
+}
+
+// One workgroup per instance of `list`.  Instances of up to 5 hosts and 3
+// classes run the backup instantiated for their own (K, J) (a uniform switch
+// per workgroup); the others the one of bounds KMAX, JMAX.  Same arithmetic
+// either way (the bounds only remove guards): bit-identical iterates.
+template <int KMAX, int JMAX>
+__global__ __launch_bounds__(kLdsBlock) void batch_lds_vi_kernel(const BatchInst* __restrict__ insts,
+                                                                  const int32_t* __restrict__ list,
+                                                                  float* __restrict__ V, double tol,
+                                                                  long long max_iter,
+                                                                  BatchOut* __restrict__ out) {
+  extern __shared__ float lds[];
+  __shared__ double part[kLdsBlock / kWave];
+  const int i = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
+  const BatchInst& I = insts[i];
+  switch (I.M.J <= 3 ? I.M.K * 4 + I.M.J : 0) {
+#define MDPVI_LDS_CASE(K_, J_) \
+  case K_ * 4 + J_: lds_solve<K_, J_>(I, i, lds, part, V, tol, max_iter, out); return;
+    MDPVI_LDS_CASE(1, 1) MDPVI_LDS_CASE(1, 2) MDPVI_LDS_CASE(1, 3)
+    MDPVI_LDS_CASE(2, 1) MDPVI_LDS_CASE(2, 2) MDPVI_LDS_CASE(2, 3)
+    MDPVI_LDS_CASE(3, 1) MDPVI_LDS_CASE(3, 2) MDPVI_LDS_CASE(3, 3)
+    MDPVI_LDS_CASE(4, 1) MDPVI_LDS_CASE(4, 2) MDPVI_LDS_CASE(4, 3)
+    MDPVI_LDS_CASE(5, 1) MDPVI_LDS_CASE(5, 2) MDPVI_LDS_CASE(5, 3)
+#undef MDPVI_LDS_CASE
+    default: lds_solve<KMAX, JMAX>(I, i, lds, part, V, tol, max_iter, out);
   }
 }
 

@@ -5,7 +5,7 @@
 
 namespace mdpvi {
 
-constexpr int kLdsBlock = 512;        // threads of an LDS-resident instance solve
+constexpr int kLdsBlock = 1024;       // threads of an LDS-resident instance solve
 constexpr int kBatchLanes = 8;        // residual words per instance (round form)
 constexpr size_t kLdsBudget = 160 * 1024 - 1024;  // dynamic LDS per workgroup
 

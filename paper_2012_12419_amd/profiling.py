@@ -216,6 +216,7 @@ def main(argv=None) -> int:
     s.add_argument("--command", required=True)
     s.add_argument("--trace", default=None, help="kernel_trace.csv of the same run")
     s.add_argument("--kernels", nargs="*", default=[], help="kernels to list working launches of")
+    s.add_argument("--top", type=int, default=12, help="rows of the per-kernel table")
     c = sub.add_parser("counters")
     c.add_argument("--dirs", nargs="+", required=True)
     c.add_argument("--kernels", nargs="+", required=True)
@@ -233,7 +234,7 @@ def main(argv=None) -> int:
         run_sweeps(a.kernel, a.workload, a.sweeps, a.copy_mb, a.form, a.adjoint_form)
         return 0
     if a.cmd == "stats":
-        sys.stdout.write(stats_markdown(a.csv, a.command, trace_csv=a.trace, kernels=a.kernels))
+        sys.stdout.write(stats_markdown(a.csv, a.command, top=a.top, trace_csv=a.trace, kernels=a.kernels))
         return 0
     if a.cmd == "counters":
         sys.stdout.write(counters_markdown(a.dirs, a.kernels, a.command))
