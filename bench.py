@@ -291,7 +291,7 @@ def gradient_workloads(mdpvi, n_batch: int, tol: float) -> dict:
         grads, objs, _, _, _ = b.vi_adjoint(pi, Vp, [p.J for p in insts], tol=1e-10)
         mark("adjoint_gradient")
         pig = b.policy_greedy("least_loaded")
-        Vg, _, _, _ = b.policy_eval(pig, tol=1e-12)
+        Vg, _, _, _ = b.policy_eval(pig, Vp.clone(), tol=1e-12)   # from V_pi*: V_greedy <= V*
         mark("greedy_evaluation")
         return time.perf_counter() - t0, objs, Vg, stages, rounds
 
@@ -456,7 +456,7 @@ def main() -> int:
         _, s_ev = mdp.policy_eval(pi, Vp, tol=args.eval_tol)
         mdp.policy_extract(Vp, pi=pi2, gap=None, want_gap=False)
         mdp.policy_greedy("least_loaded", pi=pig)
-        Vg.zero_()
+        Vg.copy_(Vp)   # the heuristic's evaluation starts from V_pi* (V_greedy <= V*, close to it)
         _, s_g = mdp.policy_eval(pig, Vg, tol=args.eval_tol)
         return s_vi, s_ev, s_g
 

@@ -52,7 +52,8 @@ def _batch_pipeline(mdpvi, insts):
     _batch_pipeline.rounds = rounds
     grads, objs, w, st, its = b.vi_adjoint(pi, Vp, [p.J for p in insts], tol=1e-11)
     pig = b.policy_greedy("least_loaded")
-    Vg, _, _, _ = b.policy_eval(pig, tol=1e-12)
+    # the heuristic's evaluation starts from V_pi* (V_greedy <= V*, close to it)
+    Vg, _, _, _ = b.policy_eval(pig, Vp.clone(), tol=1e-12)
     return b, pi, Vp, grads, objs, w, pig, Vg
 
 
@@ -111,7 +112,7 @@ def test_batch_gradient_equals_single_instance(mdpvi):
         g1, J1, w1, _ = mdp.vi_adjoint(pi[sl].contiguous(), Vp[sl].contiguous(), tol=1e-11)
         assert np.array_equal(np.array(g1), np.array(grads[i])), i
         assert np.array_equal(w1.cpu().numpy().view(np.uint32), w[sl].cpu().numpy().view(np.uint32)), i
-        V1, _ = mdp.policy_eval(pig[sl].contiguous(), tol=1e-12)
+        V1, _ = mdp.policy_eval(pig[sl].contiguous(), Vp[sl].clone(), tol=1e-12)
         assert np.array_equal(V1.cpu().numpy().view(np.uint64), Vg[sl].cpu().numpy().view(np.uint64)), i
 
 
@@ -192,7 +193,7 @@ def test_batch_pipeline_first_256_of_sweep(mdpvi):
         assert np.array_equal(w1.cpu().numpy().view(np.uint32), w_h[sl].view(np.uint32)), i
         pg1 = mdp.policy_greedy("least_loaded")
         assert np.array_equal(pg1.cpu().numpy(), pig_h[sl]), i
-        V1, _ = mdp.policy_eval(pig[sl].contiguous(), tol=1e-12)
+        V1, _ = mdp.policy_eval(pig[sl].contiguous(), Vp[sl].clone(), tol=1e-12)
         assert np.array_equal(V1.cpu().numpy().view(np.uint64), Vg_h[sl].view(np.uint64)), i
         # properties at any size, with the oracle's operators
         v = V32[sl].astype(np.float64)
