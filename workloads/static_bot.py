@@ -4,7 +4,7 @@ random static scenarios.  Data only: no placement or reward arithmetic.
 The example's eleven vehicular clouds have the VM capacities that label the
 per-VC reward figure (5 ... 45 VMs, 272 in all).  Its eleven bags of tasks
 need 5, 10, ..., 55 VMs (330 in all).  The task granularity inside a bag is
-not stated.  This build reads bag i (1-based) as five tasks of i VMs each,
+not stated.  Bag i (1-based) is read here as five tasks of i VMs each,
 the only one of the readings tried that reproduces the published greedy
 figure exactly: per-bag VC VMs, the 85 paid VMs (30 of bag 10, all 55 of bag
 11), the 27 idle VMs and each per-VC reward.
