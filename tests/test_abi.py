@@ -128,3 +128,56 @@ def test_tile_form_only_below_2gib_values(K, C, J):
             assert is_tile(vi_f.value)
     finally:
         lib.mdp_free(h)
+
+
+def test_adjoint_form_choice_on_the_host():
+    """mdp_set_adjoint_form validates forms against the shape; the automatic
+    form is the group form where it applies (C <= 15, K 3..8, J <= 3)."""
+    lib = mdpvi.load()
+    rc, h = _build(K=5, C=10)
+    assert rc == mdpvi.OK
+    try:
+        assert lib.mdp_adjoint_form(h) == mdpvi.ADJOINT_GROUP
+        for bad in (3, 5, 16 + 3, 33, -1):
+            assert lib.mdp_set_adjoint_form(h, bad) == mdpvi.EINVAL, bad
+        for good in (mdpvi.ADJOINT_EXACT + 1, mdpvi.ADJOINT_EXACT + 4, 1, 2, 4, mdpvi.ADJOINT_GROUP):
+            assert lib.mdp_set_adjoint_form(h, good) == mdpvi.OK, good
+            assert lib.mdp_adjoint_form(h) == good
+        assert lib.mdp_set_adjoint_form(h, 0) == mdpvi.OK
+    finally:
+        lib.mdp_free(h)
+    rc, h = _build(K=3, C=16, size=[1], lam=[1.0], reward=[1.0])
+    assert rc == mdpvi.OK
+    try:
+        assert lib.mdp_adjoint_form(h) == mdpvi.ADJOINT_EXACT + 1   # (C+1)^2 = 289 > 256
+        assert lib.mdp_set_adjoint_form(h, mdpvi.ADJOINT_GROUP) == mdpvi.EINVAL
+    finally:
+        lib.mdp_free(h)
+
+
+def test_batch_round_form_choice_on_the_host():
+    """batch_set_round_form validates the operation and the occupancies per
+    thread; with nothing recorded every operation uses 4."""
+    import workloads as W
+    lib = mdpvi.load()
+    insts = W.batch(6, seed=11)
+    arr = (mdpvi.Params * len(insts))()
+    keep = []
+    for i, p in enumerate(insts):
+        arr[i], k = mdpvi.make_params(p.K, p.C, p.size, p.lam, p.mu, p.nu, p.reward, p.gamma,
+                                      p.reject_cost, p.idle_unit_cost)
+        keep.append(k)
+    h = ctypes.c_void_p()
+    assert lib.mdp_build_batch(arr, len(insts), ctypes.byref(h)) == mdpvi.OK
+    try:
+        out = (ctypes.c_int32 * 3)()
+        assert lib.batch_round_forms(h, out) == mdpvi.OK
+        assert list(out) == [4, 4, 4]
+        for op, opt in ((-1, 1), (3, 1), (0, 3), (1, 8), (2, -1)):
+            assert lib.batch_set_round_form(h, op, opt) == mdpvi.EINVAL, (op, opt)
+        assert lib.batch_set_round_form(h, 0, 1) == mdpvi.OK
+        assert lib.batch_set_round_form(h, 2, 2) == mdpvi.OK
+        assert lib.batch_round_forms(h, out) == mdpvi.OK
+        assert list(out) == [1, 4, 2]
+    finally:
+        lib.mdp_free_batch(h)
