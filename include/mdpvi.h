@@ -300,10 +300,11 @@ int vi_solve_bsdi(mdpvi_mdp_t h, float *V, double tol, int64_t max_iter, int32_t
  * tile, w > 0 launches w workgroups per CU that walk their XCD's tiles in
  * order.  The automatic choice requires at least 256 occupancies per tile
  * and 256 tiles.  Tiles are handed to the XCDs in a host-computed order:
- * recursive coordinate bisection of the tile grid when the sweep's working
- * set fits 256 MB, runs of 16 tiles dealt round-robin beyond; the
- * environment variable MDPVI_TILE_ORDER (read at every solve; a measurement
- * aid) forces "index" (contiguous eighths), "rcb" or "dealN" (runs of N).
+ * the one mdp_autotune recorded for the shape, else recursive coordinate
+ * bisection of the tile grid when the sweep's working set fits 256 MB and
+ * runs of 16 tiles dealt round-robin beyond; the environment variable
+ * MDPVI_TILE_ORDER (read at every solve; a measurement aid) forces "index"
+ * (contiguous eighths), "rcb" or "dealN" (runs of N).
  * Every order and every w give bit-identical iterates.
  * MDPVI_FORM_ROW + w (w = 0..8): the row form of the value-iteration tile
  * sweep (tiles of T = 3 digits, each lane a chunk of four consecutive
@@ -398,11 +399,15 @@ int mdp_sweep_forms(mdpvi_mdp_t h, int32_t *vi, int32_t *eval);
  *   value iteration (direct, LDS slabs of 1..K-1 low digits that fit 64 KB,
  *     tile and row forms with 0..4 workgroups per CU), from V;
  *   FP64 evaluation (direct, tile with 0..5 workgroups per CU) and
- *   the adjoint sweep (generic and exact-shape kernels, 1, 2 or 4
- *     occupancies per thread), both on the least-loaded policy
+ *   the adjoint sweep (group form, generic and exact-shape kernels with 1,
+ *     2 or 4 occupancies per thread), both on the least-loaded policy;
+ * and, when a tile or row form wins, that form under each tile order (the
+ * assignment of tiles to the 8 XCDs: recursive coordinate bisection, index
+ * order, runs of 16 or of (C+1)^2 consecutive tiles dealt round-robin);
  * (V: device float[N], read only; the sweeps write the handle's scratch and
- * temporary buffers), keeps each operation's form with the smallest median
- * time and records it for the shape (GPU arch, K, C, J, sizes): later calls
+ * temporary buffers), keeps each operation's form (and tile order) with the
+ * smallest median time and records it for the shape (GPU arch, K, C, J,
+ * sizes): later calls
  * in automatic mode on any handle of that shape use it (vi_solve,
  * policy_eval, vi_adjoint and the calls built on them).  When the
  * environment variable MDPVI_AUTOTUNE_CACHE names a file, the records are

@@ -289,20 +289,38 @@ int adjoint_form(mdpvi_mdp* h) {
 // neighbour planes then stay in the last-level cache).
 constexpr uint32_t kDealRun = 16;
 
+// Tile-order codes (the tuning cache's "vi-order" and "eval-order"
+// entries): kOrderRcb recursive coordinate bisection, kOrderIndex contiguous
+// eighths of the index order, N >= 2 runs of N tiles dealt round-robin.
+constexpr int kOrderRcb = 0;
+constexpr int kOrderIndex = 1;
+
 // Points S->order at the handle's device copy of the tile order for S's tile
-// depth and a sweep working set of ws bytes, built and uploaded on first
-// use.  The environment variable MDPVI_TILE_ORDER (a measurement aid)
-// overrides the choice: "index" (contiguous eighths of the index order),
-// "rcb", or "dealN" (runs of N tiles dealt round-robin).
-int set_tile_order(mdpvi_mdp* h, mdpvi::TileShape* S, double ws) {
-  const char* env = std::getenv("MDPVI_TILE_ORDER");
-  const std::string forced(env ? env : "");
+// depth, built and uploaded on first use.  The order is `force` when it is a
+// code (>= 0); else the one the environment variable MDPVI_TILE_ORDER names
+// (a measurement aid: "index", "rcb" or "dealN"); else the one mdp_autotune
+// recorded for operation op ("vi" or "eval") and this shape; else bisection
+// for a sweep working set of ws bytes within the last-level cache and dealt
+// runs of kDealRun tiles beyond it.
+int set_tile_order(mdpvi_mdp* h, mdpvi::TileShape* S, double ws, const char* op, int force = -1) {
+  int code = ws <= kLlcBytes ? kOrderRcb : static_cast<int>(kDealRun);
+  if (force >= 0) {
+    code = force;
+  } else {
+    const char* env = std::getenv("MDPVI_TILE_ORDER");
+    const std::string forced(env ? env : "");
+    if (forced == "index") code = kOrderIndex;
+    else if (forced == "rcb") code = kOrderRcb;
+    else if (forced.rfind("deal", 0) == 0) code = std::max(2, std::atoi(forced.c_str() + 4));
+    else {
+      const int cached = tune_lookup(h->M, (std::string(op) + "-order").c_str());
+      if (cached >= 0) code = cached;
+    }
+  }
   S->order = nullptr;
-  if (forced == "index") return MDPVI_OK;
+  if (code == kOrderIndex) return MDPVI_OK;
   if (S->T < 2 || S->T > 4) return fail(MDPVI_EINVAL, "tile depth %d outside [2, 4]", S->T);
-  uint32_t run = ws <= kLlcBytes ? 0u : kDealRun;   // 0: bisection
-  if (forced == "rcb") run = 0;
-  if (forced.rfind("deal", 0) == 0) run = static_cast<uint32_t>(std::max(1, std::atoi(forced.c_str() + 4)));
+  const uint32_t run = code == kOrderRcb ? 0u : static_cast<uint32_t>(code);   // 0: bisection
   uint32_t*& d = h->tile_order[S->T - 2][run ? 1 : 0];
   uint32_t& d_run = h->tile_order_run[S->T - 2];
   if (d && run && d_run != run) {   // another dealt run length was forced
@@ -806,7 +824,7 @@ int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream
     mdpvi::TileShape Sr{};
     if (mdpvi::vi_row_shape(M, &Sr))
       for (int w = 0; w <= 4; ++w) forms.push_back(MDPVI_FORM_ROW + w);
-    rc = set_tile_order(h, &S, vi_working_set(M));
+    rc = set_tile_order(h, &S, vi_working_set(M), "vi");
     if (rc) return rc;
   }
   float* out = static_cast<float*>(h->vbuf);
@@ -841,6 +859,28 @@ int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream
   tune_record(M, "vi", best, best_t);
   if (best_form) *best_form = best;
   if (best_us) *best_us = best_t;
+  // the tile order (the assignment of tiles to XCDs) of the best tile or row
+  // form: bisection, index order, dealt runs of 16 and of (C+1)^2 tiles
+  if (is_tile_form(best) || is_row_form(best)) {
+    const bool row = is_row_form(best);
+    mdpvi::tile_set_walkers(&S, form_walkers(best), cu_count());
+    int obest = -1;
+    double obest_t = 1e300;
+    for (int code : {kOrderRcb, kOrderIndex, 16, M.R * M.R}) {
+      if ((rc = set_tile_order(h, &S, vi_working_set(M), "vi", code))) return rc;
+      auto sweep = [&]() -> hipError_t {
+        return row ? mdpvi::launch_vi_row(M, S, V, out, A[0], A[1], h->ctl, h->res, 0, 1.0, s)
+                   : mdpvi::launch_vi_tile(M, S, V, out, A[0], A[1], h->ctl, h->res, 0, 1.0, s);
+      };
+      double us = 0.0;
+      if ((rc = time_form(sweep, &us))) return rc;
+      if (us < obest_t) {
+        obest_t = us;
+        obest = code;
+      }
+    }
+    tune_record(M, "vi-order", obest, obest_t);
+  }
 
   // ---- FP64 evaluation (direct form, tile form with 0..5 workgroups per CU)
   // and the adjoint sweep (generic and exact-shape kernels, 1, 2 or 4
@@ -874,7 +914,7 @@ int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream
       }
       Ae[0] = h->abuf;
       Ae[1] = h->abuf + per;
-      int orc = set_tile_order(h, &Se, eval_working_set(M));
+      int orc = set_tile_order(h, &Se, eval_working_set(M), "eval");
       if (orc) return orc;
       HIP_TRY(mdpvi::launch_eval_arrival_init(M, ev[0], Ae[0], s));
     }
@@ -897,6 +937,26 @@ int mdp_autotune(mdpvi_mdp_t h, const float* V, int32_t trials, void* hip_stream
       }
     }
     tune_record(M, "eval", ebest, ebest_t);
+    if (is_tile_form(ebest)) {
+      mdpvi::tile_set_walkers(&Se, ebest - MDPVI_FORM_TILE, cu_count());
+      int obest = -1;
+      double obest_t = 1e300;
+      for (int code : {kOrderRcb, kOrderIndex, 16, M.R * M.R}) {
+        int orc = set_tile_order(h, &Se, eval_working_set(M), "eval", code);
+        if (orc) return orc;
+        auto sweep = [&]() -> hipError_t {
+          return mdpvi::launch_eval_tile(M, Se, pol, ev[0], ev[1], Ae[0], Ae[1], h->ctl, h->res, 0, 1.0, s);
+        };
+        double us = 0.0;
+        int trc = time_form(sweep, &us);
+        if (trc) return trc;
+        if (us < obest_t) {
+          obest_t = us;
+          obest = code;
+        }
+      }
+      tune_record(M, "eval-order", obest, obest_t);
+    }
     std::vector<int> aforms;
     if (mdpvi::adjoint_form_valid(M, mdpvi::kAdjointGroup)) aforms.push_back(mdpvi::kAdjointGroup);
     for (int opt : {1, 2, 4}) {
@@ -957,7 +1017,7 @@ int vi_solve(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, void* hip_st
     if (arc) return arc;
   }
   if (tiled) {
-    int orc = set_tile_order(h, &S, vi_working_set(M));
+    int orc = set_tile_order(h, &S, vi_working_set(M), "vi");
     if (orc) return orc;
   }
   if (is_row_form(form))
@@ -1167,7 +1227,7 @@ int vi_solve_bsdi(mdpvi_mdp_t h, float* V, double tol, int64_t max_iter, int32_t
   double* A[2] = {nullptr, nullptr};
   rc = arrival_arrays(h, V, s, A);
   if (rc) return rc;
-  rc = set_tile_order(h, &S, vi_working_set(M));
+  rc = set_tile_order(h, &S, vi_working_set(M), "vi");
   if (rc) return rc;
   return run_loop<float>(h, V, tol, max_iter, s, st, 8.0 * M.n_states,
                          static_cast<double>(h->feasible_pairs) * inner,
@@ -1227,7 +1287,7 @@ int eval_run(mdpvi_mdp* h, const uint8_t* pi, double* V, double tol, int64_t max
       return fail(MDPVI_ENOMEM, "hipMalloc of the arrival-term arrays failed");
     }
     double* A[2] = {h->abuf, h->abuf + per};
-    int orc = set_tile_order(h, &S, eval_working_set(M));
+    int orc = set_tile_order(h, &S, eval_working_set(M), "eval");
     if (orc) return orc;
     HIP_TRY(mdpvi::launch_eval_arrival_init(M, V, A[0], s));
     return run_loop<double>(h, V, tol, max_iter, s, st, 17.0 * M.n_states,

@@ -525,6 +525,11 @@ def test_autotune_cache(mdpvi, tmp_path):
             assert len(key) == 1, (op, list(data))
             rec[op] = data[key[0]]
             print(f"tuned {op}: form {rec[op][0]}, {rec[op][1]:.2f} us per sweep", flush=True)
+        for op in ("vi-order", "eval-order"):   # recorded when a tile or row form won
+            key = [k for k in data if k.startswith(op + "|")]
+            if key:
+                print(f"tuned {op}: {data[key[0]]}", flush=True)
+                assert data[key[0]][0] in (0, 1, 16, 121), data[key[0]]
         assert rec["vi"][0] == form
         b = mdpvi.MDP.from_instance(inst)   # another handle of the shape
         vi_f, ev_f = b.sweep_forms()
@@ -541,5 +546,39 @@ def test_autotune_cache(mdpvi, tmp_path):
             b.policy_eval(pi, Ve, tol=1e-10)
             outs.append((V.cpu().numpy().view(np.uint32), Ve.cpu().numpy().view(np.uint64)))
         assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    finally:
+        del os.environ["MDPVI_AUTOTUNE_CACHE"]
+
+
+def test_autotune_records_tile_orders(mdpvi, tmp_path):
+    """At the 5.3-million-state instance the tile form wins, and the
+    autotuner also records the tile order (XCD assignment) of value
+    iteration and evaluation; a solve in the tuned order and one forced to
+    the index order give the same bits."""
+    import json
+    import os
+    import torch
+    path = tmp_path / "tune.json"
+    os.environ["MDPVI_AUTOTUNE_CACHE"] = str(path)
+    try:
+        inst = W.large_single()
+        a = mdpvi.MDP.from_instance(inst)
+        a.autotune(trials=3)
+        data = json.loads(path.read_text())
+        orders = {op: [v for k, v in data.items() if k.startswith(op + "|") and "K=6|C=10|J=3" in k]
+                  for op in ("vi-order", "eval-order")}
+        print("tuned orders", orders, flush=True)
+        assert all(len(v) == 1 and v[0][0] in (0, 1, 16, 121) for v in orders.values()), orders
+        outs = []
+        for forced in (None, "index"):
+            if forced:
+                os.environ["MDPVI_TILE_ORDER"] = forced
+            try:
+                V = torch.zeros(a.num_states, device="cuda")
+                a.vi_solve(V, tol=1e-3)
+                outs.append(V.cpu().numpy().view(np.uint32))
+            finally:
+                os.environ.pop("MDPVI_TILE_ORDER", None)
+        assert np.array_equal(outs[0], outs[1])
     finally:
         del os.environ["MDPVI_AUTOTUNE_CACHE"]
