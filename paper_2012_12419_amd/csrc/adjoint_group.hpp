@@ -145,8 +145,9 @@ __device__ __forceinline__ bool adjoint_group_block(const Model& M, const uint8_
     }
   }
 
-  // reset line sums, per class in the order k = 0..K-1, x = 0..C; the lines
-  // of further zero high digits are loaded for every class at once
+  // reset term, per class: each line summed from zero in the order x =
+  // 0..C, the lines added in the order k = 0..K-1; the lines of further
+  // zero high digits are loaded for every class at once
   double rs[J];
 #pragma unroll
   for (int e = 0; e < J; ++e) rs[e] = 0.0;
@@ -160,16 +161,20 @@ __device__ __forceinline__ bool adjoint_group_block(const Model& M, const uint8_
         float v[kLineLoads];
 #pragma unroll
         for (int x = 0; x < kLineLoads; ++x) v[x] = ws[e][static_cast<uint32_t>(x) <= C ? pos + x * st : pos];
+        double line = 0.0;
 #pragma unroll
         for (int x = 0; x < kLineLoads; ++x)
-          if (static_cast<uint32_t>(x) <= C) rs[e] += static_cast<double>(v[x]);
+          if (static_cast<uint32_t>(x) <= C) line += static_cast<double>(v[x]);
+        rs[e] += line;
       }
     } else if (k == k1) {
 #pragma unroll
       for (int e = 0; e < J; ++e) {
+        double line = 0.0;
 #pragma unroll
         for (int x = 0; x < kLineLoads; ++x)
-          if (static_cast<uint32_t>(x) <= C) rs[e] += static_cast<double>(h1[e][x]);
+          if (static_cast<uint32_t>(x) <= C) line += static_cast<double>(h1[e][x]);
+        rs[e] += line;
       }
     } else {
       const uint32_t st = static_cast<uint32_t>(M.stride[k]);
@@ -183,9 +188,11 @@ __device__ __forceinline__ bool adjoint_group_block(const Model& M, const uint8_
       }
 #pragma unroll
       for (int e = 0; e < J; ++e) {
+        double line = 0.0;
 #pragma unroll
         for (int x = 0; x < kLineLoads; ++x)
-          if (static_cast<uint32_t>(x) <= C) rs[e] += static_cast<double>(v[e][x]);
+          if (static_cast<uint32_t>(x) <= C) line += static_cast<double>(v[e][x]);
+        rs[e] += line;
       }
     }
   }

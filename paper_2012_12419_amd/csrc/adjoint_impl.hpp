@@ -59,7 +59,9 @@ __device__ __forceinline__ double adjoint_occupancy(const Model& M, const uint8_
           const Idx st = static_cast<Idx>(M.stride[k]);
           if (n[k] < M.C) acc = fma(M.mu_L * (n[k] + 1), static_cast<double>(win[base + st]), acc);
           if (n[k] == 0) {
-            for (int x = 0; x <= M.C; ++x) rs += static_cast<double>(win[base + static_cast<Idx>(x) * st]);
+            double line = 0.0;
+            for (int x = 0; x <= M.C; ++x) line += static_cast<double>(win[base + static_cast<Idx>(x) * st]);
+            rs += line;
           }
         }
       }
@@ -81,12 +83,20 @@ __device__ __forceinline__ double adjoint_occupancy(const Model& M, const uint8_
 // weight of a predecessor that does not apply is adding +0.0 to a sum of
 // non-negative terms and a release from a full host multiplies by 0.0: the
 // sums are those of adjoint_occupancy, term by term and in the same order.
+//
+// ls (LINES = true): the reset lines' sums are taken from a table instead of
+// being summed here.  ls[(k J + e) nl + i], nl = n_occ / (C+1), holds the sum
+// of class e's weights along the line i of digit k, summed from zero in the
+// order x = 0..C (the order used here).  Line i of digit k has the
+// occupancies whose other digits give i as a number with digit k removed:
+// i = sum_{h<k} n_h (C+1)^h + sum_{h>k} n_h (C+1)^(h-1).
 constexpr int kLineLoads = 16;
 
-template <int K, int J>
+template <int K, int J, bool LINES = false>
 __device__ __forceinline__ double adjoint_occupancy_exact(const Model& M, const uint8_t* __restrict__ pi,
                                                           const float* __restrict__ win,
-                                                          float* __restrict__ wout, uint32_t o) {
+                                                          float* __restrict__ wout, uint32_t o,
+                                                          const double* __restrict__ ls = nullptr) {
   const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
   int n[K];
   decode<K>(M, o, n);
@@ -114,6 +124,33 @@ __device__ __forceinline__ double adjoint_occupancy_exact(const Model& M, const 
       w_rel[k][e] = win[n[k] < M.C ? s0 + st[k] : s0];
     }
   }
+  // the line sums of the digits with n_k = 0 (a load under a branch that
+  // waits nowhere: the sums are used after every load is issued)
+  double lsum[K][J];
+  if constexpr (LINES) {
+    const uint32_t nl = fast_div(nocc, M.divR);
+    uint32_t idx[K];
+    uint32_t below = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      idx[k] = below;
+      below += static_cast<uint32_t>(n[k]) * st[k];
+    }
+    uint32_t above = 0;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) {
+      idx[k] += above;
+      if (k > 0) above += static_cast<uint32_t>(n[k]) * st[k - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int e = 0; e < J; ++e) {
+        lsum[k][e] = 0.0;
+        if (n[k] == 0) lsum[k][e] = ls[static_cast<uint32_t>(k * J + e) * nl + idx[k]];
+      }
+    }
+  }
   double B = 0.0;
 #pragma unroll
   for (int e = 0; e < J; ++e) B += p_own[e] == M.K ? static_cast<double>(w_own[e]) : 0.0;
@@ -136,15 +173,21 @@ __device__ __forceinline__ double adjoint_occupancy_exact(const Model& M, const 
       if (n[k] == 0) {
         // the line sum along digit k, in order x = 0..C; lines of up to
         // kLineLoads values are loaded all at once
-        if (M.C < kLineLoads) {
+        if constexpr (LINES) {
+          rs += lsum[k][e];
+        } else if (M.C < kLineLoads) {
           float v[kLineLoads];
 #pragma unroll
           for (int x = 0; x < kLineLoads; ++x) v[x] = win[base + (x <= M.C ? static_cast<uint32_t>(x) * st[k] : 0u)];
+          double line = 0.0;
 #pragma unroll
           for (int x = 0; x < kLineLoads; ++x)
-            if (x <= M.C) rs += static_cast<double>(v[x]);
+            if (x <= M.C) line += static_cast<double>(v[x]);
+          rs += line;
         } else {
-          for (int x = 0; x <= M.C; ++x) rs += static_cast<double>(win[base + static_cast<uint32_t>(x) * st[k]]);
+          double line = 0.0;
+          for (int x = 0; x <= M.C; ++x) line += static_cast<double>(win[base + static_cast<uint32_t>(x) * st[k]]);
+          rs += line;
         }
       }
     }

@@ -687,6 +687,8 @@ struct mdpvi_batch {
   int* h_active = nullptr;                      // pinned
   uint8_t* d_pbuf = nullptr;                    // policy scratch (round check), on first use
   int64_t a_total = 0;                          // their length: sum of n_occ + 1
+  double* d_lines = nullptr;                    // the adjoint's reset-line sums (BatchInst::loff)
+  int64_t l_total = 0;                          // their length: sum of K J n_occ / (C+1)
   mdpvi::BatchOut* d_out = nullptr;
   float* W = nullptr;               // ping-pong partner of the concatenated values
   int* h_remaining = nullptr;       // pinned
@@ -1487,6 +1489,7 @@ int ensure_batch_device(mdpvi_batch* b) {
     inst[i].M = b->models[i];
     inst[i].offset = b->offsets[i];
     inst[i].aoff = -1;
+    inst[i].loff = -1;
     inst[i].lds = 0;
     inst[i].ctl = -1;
   }
@@ -1495,6 +1498,15 @@ int ensure_batch_device(mdpvi_batch* b) {
   for (int32_t i : b->round_list) {
     inst[i].aoff = b->a_total;
     b->a_total += b->models[i].n_occ + 1;
+  }
+  // line tables for the instances whose adjoint rounds take the exact backup
+  b->l_total = 0;
+  for (int i = 0; i < n; ++i) {
+    const mdpvi::Model& M = b->models[i];
+    if (M.K <= mdpvi::kBatchExactK && M.J <= 3) {
+      inst[i].loff = b->l_total;
+      b->l_total += static_cast<int64_t>(M.K) * M.J * (M.n_occ / M.R);
+    }
   }
   for (int i = 0; i < n; ++i) inst[i].ctl = i;
   n_ctl = n;
@@ -1526,6 +1538,7 @@ int ensure_batch_device(mdpvi_batch* b) {
     if ((rc = dalloc(reinterpret_cast<void**>(&b->d_act[a]),
                      std::max<size_t>(b->rtiles_all[0].size(), 1) * sizeof(mdpvi::Tile))))
       return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_lines), b->l_total * sizeof(double)))) return rc;
   for (int a = 0; a < 2; ++a) {
     if ((rc = dalloc(reinterpret_cast<void**>(&b->d_A[a]), b->a_total * sizeof(double)))) return rc;
     if ((rc = dalloc(reinterpret_cast<void**>(&b->d_active[a]), n * sizeof(int)))) return rc;
@@ -1680,6 +1693,7 @@ void mdp_free_batch(mdpvi_batch_t b) {
   (void)hipFree(b->d_act[1]);
   (void)hipFree(b->d_A[0]);
   (void)hipFree(b->d_A[1]);
+  (void)hipFree(b->d_lines);
   (void)hipFree(b->d_active[0]);
   (void)hipFree(b->d_active[1]);
   if (b->h_active) (void)hipHostFree(b->h_active);
@@ -2051,7 +2065,7 @@ int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t* pi, const double* V_pi, flo
       b, opt, tol, max_iter, s, st, iterations, nullptr, 9.0,
       [&](long long j, const mdpvi::Tile* tiles, int n) {
         return mdpvi::launch_batch_adjoint_round(b->d_inst, tiles, n, b->maxK, b->maxJ, pi, w, b->W,
-                                                 b->d_ctl, b->d_remaining, j, tol, opt, s);
+                                                 b->d_ctl, b->d_remaining, j, tol, opt, b->d_lines, s);
       },
       [&](int64_t issued) {
         return mdpvi::launch_batch_adjoint_finish(b->d_inst, b->d_all, b->n, w, b->W, b->d_ctl, issued, b->d_out,
@@ -2135,7 +2149,7 @@ int batch_autotune(mdpvi_batch_t b, int32_t trials, void* hip_stream, int32_t* o
             return mdpvi::launch_batch_eval_round(b->d_inst, tiles, nt, b->maxK, b->maxJ, pol, v64, w64, b->d_ctl,
                                                   b->d_remaining, 0, 1.0, o, s);
           return mdpvi::launch_batch_adjoint_round(b->d_inst, tiles, nt, b->maxK, b->maxJ, pol, v32, b->W,
-                                                   b->d_ctl, b->d_remaining, 0, 1.0, o, s);
+                                                   b->d_ctl, b->d_remaining, 0, 1.0, o, b->d_lines, s);
         };
         std::vector<float> ms(trials);
         for (int r = -1; r < trials; ++r) {   // r = -1: untimed first launch

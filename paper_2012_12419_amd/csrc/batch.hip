@@ -111,13 +111,16 @@ __global__ __launch_bounds__(kLdsBlock) void batch_lds_vi_kernel(const BatchInst
 // KM, JM), run_exact the exact-shape one (K hosts and J classes known at
 // compile time, every load issued before the first use), which gives the
 // same bits; exact_ok tells whether an instance meets run_exact's terms.
-// Value iteration's exact backup reads the FP64 arrival terms of the
-// previous round from the instance's side array (ain: n_occ entries and a
-// -inf entry for placements without room) and writes this round's (aout).
+// side() picks the exact backup's side arrays from the launch's A0 / A1 for
+// round j and returns false when the launch brings none it needs (the
+// generic backup then runs).  Value iteration's exact backup reads the FP64
+// arrival terms of the previous round from the instance's side array (ain:
+// n_occ entries and a -inf entry for placements without room) and writes
+// this round's (aout); the adjoint's reads the reset-line sums of its input
+// (ain, A0 = the line table; batch_line_sum_kernel).
 struct VIOp {
   using T = float;
   static constexpr ResKind RK = ResKind::kMax;
-  static constexpr bool kSideArrays = true;
   template <int KM, int JM>
   __device__ static double run(const Model& M, const uint8_t*, const T* in, T* out, uint32_t o) {
     return backup_occupancy<KM, JM, uint32_t>(M, in, out, o);
@@ -125,6 +128,13 @@ struct VIOp {
   __device__ static bool exact_ok(const BatchInst& I) {
     const Model& M = I.M;
     return I.aoff >= 0 && M.n_states < (int64_t{1} << 29) && M.J <= 3 && M.n_sizes == M.J;
+  }
+  __device__ static bool side(const BatchInst& I, long long j, double* A0, double* A1, const double** ain,
+                              double** aout) {
+    if (A0 == nullptr) return false;
+    *ain = ((j & 1) ? A1 : A0) + I.aoff;
+    *aout = ((j & 1) ? A0 : A1) + I.aoff;
+    return true;
   }
   template <int K, int J>
   __device__ static double run_exact(const Model& M, const uint8_t*, const T* in, T* out, const double* ain,
@@ -136,7 +146,9 @@ struct VIOp {
 struct EvalOp {
   using T = double;
   static constexpr ResKind RK = ResKind::kMax;
-  static constexpr bool kSideArrays = false;
+  __device__ static bool side(const BatchInst&, long long, double*, double*, const double**, double**) {
+    return true;
+  }
   template <int KM, int JM>
   __device__ static double run(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
     return eval_occupancy<KM, JM, uint32_t>(M, pi, in, out, o);
@@ -152,21 +164,93 @@ struct EvalOp {
 struct AdjOp {
   using T = float;
   static constexpr ResKind RK = ResKind::kSum;
-  static constexpr bool kSideArrays = false;
   template <int KM, int JM>
   __device__ static double run(const Model& M, const uint8_t* pi, const T* in, T* out, uint32_t o) {
     return adjoint_occupancy<KM, JM, uint32_t>(M, pi, in, out, o);
   }
-  __device__ static bool exact_ok(const BatchInst& I) { return I.M.J <= 3; }
+  __device__ static bool exact_ok(const BatchInst& I) { return I.M.J <= 3 && I.loff >= 0; }
+  __device__ static bool side(const BatchInst& I, long long, double* A0, double*, const double** ain,
+                              double**) {
+    if (A0 == nullptr) return false;
+    *ain = A0 + I.loff;
+    return true;
+  }
   template <int K, int J>
-  __device__ static double run_exact(const Model& M, const uint8_t* pi, const T* in, T* out, const double*,
+  __device__ static double run_exact(const Model& M, const uint8_t* pi, const T* in, T* out, const double* lines,
                                      double*, uint32_t o) {
-    return adjoint_occupancy_exact<K, J>(M, pi, in, out, o);
+    return adjoint_occupancy_exact<K, J, true>(M, pi, in, out, o, lines);
   }
 };
 
-// Host counts up to which the round kernels carry exact-shape backups.
-constexpr int kBatchExactK = 5;
+// Sum of the N weights win[base + x st], x = 0..N-1, from zero in that order
+// (all N loads issued before the first add).
+template <int N>
+__device__ __forceinline__ double line_sum(const float* __restrict__ win, uint32_t base, uint32_t st) {
+  float v[N];
+#pragma unroll
+  for (int x = 0; x < N; ++x) v[x] = win[base + static_cast<uint32_t>(x) * st];
+  double line = 0.0;
+#pragma unroll
+  for (int x = 0; x < N; ++x) line += static_cast<double>(v[x]);
+  return line;
+}
+
+// The reset-line sums of the adjoint's input for round j (the table the
+// exact adjoint backup reads, layout in adjoint_occupancy_exact): for the
+// tile's instance, every digit k, class e and line i in [ceil(first / R),
+// ceil(end / R)) with R = C+1 -- the tiles of an instance partition
+// [0, n_occ), so these ranges partition its n_occ / R lines -- the sum of
+// w along the line, from zero in the order x = 0..C.  Consecutive threads
+// take consecutive lines of one (k, e): along a high digit their loads are
+// consecutive addresses.  A line's base (n_k = 0) is i with a zero digit
+// inserted at k.
+__global__ __launch_bounds__(kBlock) void batch_line_sum_kernel(const BatchInst* __restrict__ insts,
+                                                                 const Tile* __restrict__ tiles,
+                                                                 const float* __restrict__ w,
+                                                                 const float* __restrict__ W,
+                                                                 BatchCtl* __restrict__ ctl, long long j,
+                                                                 double* __restrict__ lines, int opt) {
+  const Tile tile = tiles[blockIdx.x];
+  const BatchInst& I = insts[tile.inst];
+  if (I.loff < 0) return;
+  // an instance that already stopped (done_iter only changes in round
+  // kernels, never while this one runs: the same answer for every lane)
+  if (load_agent(&ctl[tile.inst].done_iter) >= 0) return;
+  const Model& M = I.M;
+  const float* win = ((j & 1) ? W : w) + I.offset;
+  double* L = lines + I.loff;
+  const uint32_t R = static_cast<uint32_t>(M.R), C = static_cast<uint32_t>(M.C);
+  const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
+  const uint32_t end = min(tile.first + static_cast<uint32_t>(kBlock * opt), nocc);
+  const uint32_t i0 = fast_div(tile.first + R - 1, M.divR);
+  const uint32_t cnt = fast_div(end + R - 1, M.divR) - i0;
+  const uint32_t nl = fast_div(nocc, M.divR);
+  const uint32_t total = cnt * static_cast<uint32_t>(M.K * M.J);
+  for (uint32_t u = threadIdx.x; u < total; u += kBlock) {
+    const uint32_t ke = u / cnt;
+    const uint32_t i = i0 + (u - ke * cnt);
+    const uint32_t k = ke / static_cast<uint32_t>(M.J);
+    const uint32_t e = ke - k * static_cast<uint32_t>(M.J);
+    uint32_t hi = i;
+    for (uint32_t h = 0; h < k; ++h) hi = fast_div(hi, M.divR);
+    const uint32_t st = static_cast<uint32_t>(M.stride[k]);
+    const uint32_t base = hi * st * R + (i - hi * st) + e * nocc;
+    double line;
+    switch (C) {
+#define MDPVI_LINE_CASE(C_) \
+  case C_: line = line_sum<C_ + 1>(win, base, st); break;
+      MDPVI_LINE_CASE(1) MDPVI_LINE_CASE(2) MDPVI_LINE_CASE(3) MDPVI_LINE_CASE(4) MDPVI_LINE_CASE(5)
+      MDPVI_LINE_CASE(6) MDPVI_LINE_CASE(7) MDPVI_LINE_CASE(8) MDPVI_LINE_CASE(9) MDPVI_LINE_CASE(10)
+      MDPVI_LINE_CASE(11) MDPVI_LINE_CASE(12) MDPVI_LINE_CASE(13) MDPVI_LINE_CASE(14) MDPVI_LINE_CASE(15)
+#undef MDPVI_LINE_CASE
+      default:
+        line = 0.0;
+        for (uint32_t x = 0; x <= C; ++x) line += static_cast<double>(win[base + x * st]);
+    }
+    L[ke * nl + i] = line;
+  }
+}
+
 
 // Per-instance control of the round form: true (for the whole workgroup) when
 // the instance already stopped.  The leader workgroup of the instance (its
@@ -249,10 +333,10 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
   double acc = 0.0;
   bool done = false;
   if constexpr (EXACT) {
-    if (Op::exact_ok(I) && (!Op::kSideArrays || A0 != nullptr)) {
+    const double* Ain = nullptr;
+    double* Aout = nullptr;
+    if (Op::exact_ok(I) && Op::side(I, j, A0, A1, &Ain, &Aout)) {
       done = true;
-      const double* Ain = A0 ? ((j & 1) ? A1 : A0) + I.aoff : nullptr;
-      double* Aout = A0 ? ((j & 1) ? A0 : A1) + I.aoff : nullptr;
       switch (M.K * 4 + M.J) {
 #define MDPVI_ROUND_CASE(K_, J_) \
   case K_ * 4 + J_: acc = round_tile_exact<Op, K_, J_>(M, p, Vin, Vout, Ain, Aout, tile.first, opt); break;
@@ -678,9 +762,18 @@ hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, in
 
 hipError_t launch_batch_adjoint_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                       int maxJ, const uint8_t* pi, float* w, float* W, BatchCtl* ctl,
-                                      int* remaining, long long j, double tol, int opt, hipStream_t s) {
-  return launch_round_t<AdjOp>(insts, tiles, n_tiles, maxK, maxJ, w, W, pi, ctl, remaining, j, tol, opt,
-                               nullptr, nullptr, s);
+                                      int* remaining, long long j, double tol, int opt, double* lines,
+                                      hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  if (opt < 1 || opt > kOccPerThread) return hipErrorInvalidValue;
+  if (lines) {
+    hipLaunchKernelGGL(batch_line_sum_kernel, dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles, w, W, ctl, j,
+                       lines, opt);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return launch_round_t<AdjOp>(insts, tiles, n_tiles, maxK, maxJ, w, W, pi, ctl, remaining, j, tol, opt, lines,
+                               nullptr, s);
 }
 
 template <typename T, ResKind RK>

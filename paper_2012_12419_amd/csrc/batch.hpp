@@ -8,12 +8,16 @@ namespace mdpvi {
 constexpr int kLdsBlock = 1024;       // threads of an LDS-resident instance solve
 constexpr int kBatchLanes = 8;        // residual words per instance (round form)
 constexpr size_t kLdsBudget = 160 * 1024 - 1024;  // dynamic LDS per workgroup
+constexpr int kBatchExactK = 5;       // host counts up to which the round kernels
+                                      // carry exact-shape backups
 
 struct BatchInst {
   Model M;
   int64_t offset;   // first state of this instance in the concatenated arrays
   int64_t aoff;     // first entry of its arrival terms (n_occ + 1 doubles) in the
                     // value-iteration side arrays; -1 when it has none
+  int64_t loff;     // first entry of its reset-line sums (K J n_occ / (C+1)
+                    // doubles) in the adjoint's line table; -1 when none
   int32_t lds;      // 1: solved LDS-resident by one workgroup
   int32_t ctl;      // index of its round-form control block (-1 if none)
 };

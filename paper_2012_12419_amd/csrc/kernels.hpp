@@ -151,9 +151,14 @@ hipError_t launch_batch_arrival_init(const BatchInst* insts, const Tile* tiles, 
 hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                    int maxJ, const uint8_t* pi, double* V, double* W, BatchCtl* ctl,
                                    int* remaining, long long j, double tol, int opt, hipStream_t s);
+// The adjoint's round: with a line table (lines != nullptr; the instances'
+// loff entries) the reset-line sums of the round's input are written to it
+// first and the exact backups read them; nullptr: every instance sums its
+// lines itself (the generic backup).
 hipError_t launch_batch_adjoint_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                       int maxJ, const uint8_t* pi, float* w, float* W, BatchCtl* ctl,
-                                      int* remaining, long long j, double tol, int opt, hipStream_t s);
+                                      int* remaining, long long j, double tol, int opt, double* lines,
+                                      hipStream_t s);
 hipError_t launch_batch_round_finish(const BatchInst* insts, const int32_t* list, int n_list,
                                      float* V, const float* W, BatchCtl* ctl, long long issued,
                                      BatchOut* out, hipStream_t s);
