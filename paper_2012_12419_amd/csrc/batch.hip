@@ -766,6 +766,8 @@ hipError_t launch_batch_adjoint_round(const BatchInst* insts, const Tile* tiles,
                                       hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   if (opt < 1 || opt > kOccPerThread) return hipErrorInvalidValue;
+  // the table is read only by the exact backups of the kernel below
+  if (!(maxK <= kBatchExactK && maxJ <= 3)) lines = nullptr;
   if (lines) {
     hipLaunchKernelGGL(batch_line_sum_kernel, dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles, w, W, ctl, j,
                        lines, opt);

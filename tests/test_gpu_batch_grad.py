@@ -221,3 +221,39 @@ def test_batch_pipeline_first_256_of_sweep(mdpvi):
         _near_optimal(p, Vp_h[sl], o["V"])
         assert np.array_equal(pig_h[sl], o["greedy"]), i
         assert np.max(np.abs(Vg_h[sl] - o["V_greedy"])) <= EVAL_REL * np.max(np.abs(o["V_greedy"])), i
+
+
+def _line_table_batch(with_k6):
+    out = [
+        W.make(1, 6, (1, 2), (0.8, 0.4), 0.1, 0.02, (1.0, 2.5), 0.95),                   # K = 1
+        W.make(2, 16, (1, 2, 3), (0.5, 0.4, 0.3), 0.1, 0.02, (1.0, 2.0, 3.0), 0.96),     # C + 1 > 16
+        W.make(5, 2, (1, 2), (0.6, 0.3), 0.1, 0.02, (1.0, 2.0), 0.95),                   # C + 1 = 3
+        W.make(5, 3, (1, 2, 3), (0.6, 0.3, 0.2), 0.1, 0.02, (1.0, 2.0, 3.5), 0.95),
+        W.make(4, 5, (2,), (1.0,), 0.1, 0.02, (2.0,), 0.95),                             # J = 1
+        W.make(3, 9, (1, 1), (0.7, 0.5), 0.1, 0.02, (1.0, 1.5), 0.97, idle_unit_cost=0.05),
+        W.gradient_instance(3, 6),
+    ]
+    if with_k6:   # a host count past the exact round backups: every instance generic
+        out.append(W.make(6, 2, (1, 2), (0.8, 0.4), 0.1, 0.02, (1.0, 2.5), 0.95))
+    return out
+
+
+@pytest.mark.parametrize("with_k6", [False, True])
+def test_batch_adjoint_line_table_equals_single_instance(mdpvi, with_k6):
+    """The batched adjoint with its precomputed reset-line sums (exact round
+    backups) and without them (a batch with K = 6 takes the generic backup)
+    gives the single-instance adjoint's bits: K = 1, lines longer than 16,
+    lines of 3, J = 1, equal task sizes."""
+    insts = _line_table_batch(with_k6)
+    b = mdpvi.Batch(insts)
+    pig = b.policy_greedy("least_loaded")
+    import torch
+    V0 = torch.zeros(b.num_states, dtype=torch.float64, device="cuda")
+    Vg, _, _, _ = b.policy_eval(pig, V0, tol=1e-12)
+    grads, objs, w, st, its = b.vi_adjoint(pig, Vg, [p.J for p in insts], tol=1e-11)
+    for i, p in enumerate(insts):
+        sl = slice(b.offsets[i], b.offsets[i + 1])
+        mdp = mdpvi.MDP.from_instance(p)
+        g1, J1, w1, _ = mdp.vi_adjoint(pig[sl].contiguous(), Vg[sl].contiguous(), tol=1e-11)
+        assert np.array_equal(w1.cpu().numpy().view(np.uint32), w[sl].cpu().numpy().view(np.uint32)), i
+        assert np.allclose(np.array(g1), np.array(grads[i]), rtol=1e-12, atol=0.0), i
