@@ -661,6 +661,15 @@ struct mdpvi_batch {
   std::vector<mdpvi::Tile> rtiles[3], rtiles_all[3];
   mdpvi::Tile* d_rtiles[3] = {nullptr, nullptr, nullptr};
   mdpvi::Tile* d_rtiles_all[3] = {nullptr, nullptr, nullptr};
+  // value iteration's tile form: tiles {inst, tile index} of the round-form
+  // instances it covers (tocc > 0), and the direct tiles of the others
+  std::vector<int32_t> tocc;             // per instance: (C+1)^3, or 0
+  std::vector<mdpvi::Tile> vt_tiles, rtiles_nt[3];
+  mdpvi::Tile* d_vt_tiles = nullptr;
+  mdpvi::Tile* d_rtiles_nt[3] = {nullptr, nullptr, nullptr};
+  mdpvi::Tile* d_vact[2] = {nullptr, nullptr};   // active-tile lists of the tile form
+  size_t vt_lds = 0;                     // dynamic LDS of the tile-form rounds
+  int vi_tile = -1;                      // tile form: -1 automatic, 0 off, 1 on
   int round_opt[3] = {0, 0, 0};          // per operation (value iteration, evaluation, adjoint):
                                          // occupancies per thread, 0 automatic
   int lds_maxK = 1, lds_maxJ = 1, rnd_maxK = 1, rnd_maxJ = 1, maxK = 1, maxJ = 1;
@@ -680,13 +689,14 @@ struct mdpvi_batch {
   double* h_gout = nullptr;         // pinned
   void* W2 = nullptr;               // FP64 ping-pong partner (evaluation), on first use
   mdpvi::BatchCtl* d_ctl = nullptr;
-  int* d_remaining = nullptr;       // [0] unfinished instances, [1] active tiles after a compaction
+  int* d_remaining = nullptr;       // [0] unfinished instances, [1] active tiles after a compaction,
+                                    // [2] active tile-form tiles
   mdpvi::Tile* d_act[2] = {nullptr, nullptr};   // active-tile lists of the round loops
   double* d_A[2] = {nullptr, nullptr};          // FP64 arrival terms of the round-form instances (VI)
   int* d_active[2] = {nullptr, nullptr};        // per-instance flags of batched policy iteration
   int* h_active = nullptr;                      // pinned
   uint8_t* d_pbuf = nullptr;                    // policy scratch (round check), on first use
-  int64_t a_total = 0;                          // their length: sum of n_occ + 1
+  int64_t a_total = 0;                          // their length: sum of n_occ + max(1, tocc)
   double* d_lines = nullptr;                    // the adjoint's reset-line sums (BatchInst::loff)
   int64_t l_total = 0;                          // their length: sum of K J n_occ / (C+1)
   mdpvi::BatchOut* d_out = nullptr;
@@ -1474,6 +1484,16 @@ int batch_opt(const mdpvi_batch* b, int op) {
 
 int opt_index(int opt) { return opt == 1 ? 0 : opt == 2 ? 1 : 2; }
 
+// Whether value iteration's rounds run the tile form for the instances it
+// covers: the mode set on the batch, else the choice batch_autotune recorded
+// for its shapes, else on.
+bool batch_vi_tile_on(const mdpvi_batch* b) {
+  if (b->vt_tiles.empty()) return false;
+  if (b->vi_tile >= 0) return b->vi_tile == 1;
+  const int cached = tune_lookup_key(batch_tune_key(b, 0) + "|tile");
+  return cached != 0;
+}
+
 int ensure_batch_device(mdpvi_batch* b) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -1491,13 +1511,15 @@ int ensure_batch_device(mdpvi_batch* b) {
     inst[i].aoff = -1;
     inst[i].loff = -1;
     inst[i].lds = 0;
+    inst[i].tocc = b->tocc[i];
+    inst[i].pad = 0;
     inst[i].ctl = -1;
   }
   for (int32_t i : b->lds_list) inst[i].lds = 1;
   b->a_total = 0;
   for (int32_t i : b->round_list) {
     inst[i].aoff = b->a_total;
-    b->a_total += b->models[i].n_occ + 1;
+    b->a_total += b->models[i].n_occ + std::max<int64_t>(1, b->tocc[i]);
   }
   // line tables for the instances whose adjoint rounds take the exact backup
   b->l_total = 0;
@@ -1533,7 +1555,14 @@ int ensure_batch_device(mdpvi_batch* b) {
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_gout), static_cast<size_t>(n) * (2 * MDPVI_MAX_J + 3) * sizeof(double))))
     return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_ctl), std::max(n_ctl, 1) * sizeof(mdpvi::BatchCtl)))) return rc;
-  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_remaining), 2 * sizeof(int)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_remaining), 3 * sizeof(int)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_vt_tiles), b->vt_tiles.size() * sizeof(mdpvi::Tile)))) return rc;
+  for (int a = 0; a < 2; ++a)
+    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_vact[a]), std::max<size_t>(b->vt_tiles.size(), 1) * sizeof(mdpvi::Tile))))
+      return rc;
+  for (int oi = 0; oi < 3; ++oi)
+    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_rtiles_nt[oi]), b->rtiles_nt[oi].size() * sizeof(mdpvi::Tile))))
+      return rc;
   for (int a = 0; a < 2; ++a)
     if ((rc = dalloc(reinterpret_cast<void**>(&b->d_act[a]),
                      std::max<size_t>(b->rtiles_all[0].size(), 1) * sizeof(mdpvi::Tile))))
@@ -1556,7 +1585,7 @@ int ensure_batch_device(mdpvi_batch* b) {
   }
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_out), n * sizeof(mdpvi::BatchOut)))) return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->W), std::max<int64_t>(b->offsets[n], 1) * sizeof(float)))) return rc;
-  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_remaining), 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_remaining), 3 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&b->h_out), n * sizeof(mdpvi::BatchOut), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&b->h_flags), n * sizeof(int), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&b->h_gout), static_cast<size_t>(n) * (2 * MDPVI_MAX_J + 3) * sizeof(double),
@@ -1577,7 +1606,13 @@ int ensure_batch_device(mdpvi_batch* b) {
                         hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(b->d_rtiles_all[oi], b->rtiles_all[oi].data(), b->rtiles_all[oi].size() * sizeof(mdpvi::Tile),
                       hipMemcpyHostToDevice));
+    if (!b->rtiles_nt[oi].empty())
+      HIP_TRY(hipMemcpy(b->d_rtiles_nt[oi], b->rtiles_nt[oi].data(), b->rtiles_nt[oi].size() * sizeof(mdpvi::Tile),
+                        hipMemcpyHostToDevice));
   }
+  if (!b->vt_tiles.empty())
+    HIP_TRY(hipMemcpy(b->d_vt_tiles, b->vt_tiles.data(), b->vt_tiles.size() * sizeof(mdpvi::Tile),
+                      hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_all, b->all_list.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_tile_begin, b->tile_begin.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
@@ -1664,6 +1699,34 @@ int mdp_build_batch(const mdpvi_params* p, int32_t n, mdpvi_batch_t* out) {
       }
     }
   }
+  // value iteration's tile form: round-form instances of 4 or 5 hosts and
+  // up to 3 classes of distinct sizes whose tile of (C+1)^3 occupancies
+  // (values and arrival terms) fits the workgroup's LDS
+  b->tocc.assign(n, 0);
+  for (int32_t i : b->round_list) {
+    const Model& M = b->models[i];
+    const int64_t occ = static_cast<int64_t>(M.R) * M.R * M.R;
+    const int64_t lds = (occ + 1) * 8 + occ * 4 * M.J;
+    // buffer views hold byte offsets below 2^31
+    const bool views = M.n_states < (int64_t{1} << 29) && M.n_occ + occ < (int64_t{1} << 28);
+    if ((M.K == 4 || M.K == 5) && M.J <= 3 && M.n_sizes == M.J && views &&
+        lds <= static_cast<int64_t>(mdpvi::kBatchTileLds))
+      b->tocc[i] = static_cast<int32_t>(occ);
+  }
+  for (int32_t i : b->round_list) {
+    const Model& M = b->models[i];
+    if (b->tocc[i] > 0) {
+      const uint32_t nt = static_cast<uint32_t>(M.n_occ / b->tocc[i]);
+      for (uint32_t t = 0; t < nt; ++t) b->vt_tiles.push_back({i, t});
+      b->vt_lds = std::max(b->vt_lds, static_cast<size_t>(b->tocc[i] + 1) * 8 +
+                                          static_cast<size_t>(b->tocc[i]) * 4 * M.J);
+    } else {
+      for (int oi = 0; oi < 3; ++oi) {
+        const uint32_t per = static_cast<uint32_t>(mdpvi::kBlock) << oi;
+        for (uint32_t t = 0; t < static_cast<uint32_t>(M.n_occ); t += per) b->rtiles_nt[oi].push_back({i, t});
+      }
+    }
+  }
   std::sort(cost.begin(), cost.end(), [](auto& x, auto& y) { return x.first > y.first; });
   for (auto& c : cost) b->lds_list.push_back(c.second);
   b->lds_bytes = static_cast<size_t>(2 * max_lds_n) * sizeof(float);
@@ -1694,6 +1757,10 @@ void mdp_free_batch(mdpvi_batch_t b) {
   (void)hipFree(b->d_A[0]);
   (void)hipFree(b->d_A[1]);
   (void)hipFree(b->d_lines);
+  (void)hipFree(b->d_vt_tiles);
+  (void)hipFree(b->d_vact[0]);
+  (void)hipFree(b->d_vact[1]);
+  for (int oi = 0; oi < 3; ++oi) (void)hipFree(b->d_rtiles_nt[oi]);
   (void)hipFree(b->d_active[0]);
   (void)hipFree(b->d_active[1]);
   if (b->h_active) (void)hipHostFree(b->h_active);
@@ -1753,22 +1820,35 @@ int vi_solve_batch(mdpvi_batch_t b, float* V, double tol, int64_t max_iter, void
   if (n_round > 0) {
     int64_t chunk = 8;
     const int opt = batch_opt(b, 0);
-    const mdpvi::Tile* tiles = b->d_rtiles[opt_index(opt)];
-    int nt = static_cast<int>(b->rtiles[opt_index(opt)].size()), cur = 0;
-    HIP_TRY(mdpvi::launch_batch_arrival_init(b->d_inst, tiles, nt, V, b->d_A[0], b->d_A[1], opt, s));
+    const int oi = opt_index(opt);
+    // every round-form instance's arrival terms (and -inf blocks)
+    HIP_TRY(mdpvi::launch_batch_arrival_init(b->d_inst, b->d_rtiles[oi], static_cast<int>(b->rtiles[oi].size()), V,
+                                             b->d_A[0], b->d_A[1], opt, s));
+    // the tile form's instances, and the direct form's (the others, or all)
+    const bool tile = batch_vi_tile_on(b);
+    const mdpvi::Tile* vtiles = tile ? b->d_vt_tiles : nullptr;
+    int nvt = tile ? static_cast<int>(b->vt_tiles.size()) : 0;
+    const mdpvi::Tile* tiles = tile ? b->d_rtiles_nt[oi] : b->d_rtiles[oi];
+    int nt = static_cast<int>(tile ? b->rtiles_nt[oi].size() : b->rtiles[oi].size()), cur = 0;
     while (issued < max_iter) {
       const int64_t m = std::min<int64_t>(chunk, max_iter - issued);
-      for (int64_t k = 0; k < m; ++k)
+      for (int64_t k = 0; k < m; ++k) {
+        HIP_TRY(mdpvi::launch_batch_vi_tile(b->d_inst, vtiles, nvt, b->vt_lds, V, b->W, b->d_ctl, b->d_remaining,
+                                            issued + k, tol, b->d_A[0], b->d_A[1], s));
         HIP_TRY(mdpvi::launch_batch_round(b->d_inst, tiles, nt, b->rnd_maxK, b->rnd_maxJ, V, b->W, b->d_ctl,
                                           b->d_remaining, issued + k, tol, opt, b->d_A[0], b->d_A[1], s));
+      }
       issued += m;
       // drop the tiles of instances that have stopped from the next chunk
       HIP_TRY(mdpvi::launch_batch_compact(tiles, nt, b->d_ctl, b->d_act[cur], b->d_remaining + 1, s));
-      HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(mdpvi::launch_batch_compact(vtiles, nvt, b->d_ctl, b->d_vact[cur], b->d_remaining + 2, s));
+      HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       if (b->h_remaining[0] <= 0) break;
       tiles = b->d_act[cur];
       nt = b->h_remaining[1];
+      vtiles = b->d_vact[cur];
+      nvt = b->h_remaining[2];
       cur ^= 1;
       if (chunk < kMaxChunk) chunk *= 2;
     }
@@ -2102,6 +2182,21 @@ int batch_round_forms(mdpvi_batch_t b, int32_t* opt) {
   return MDPVI_OK;
 }
 
+int batch_set_vi_tile(mdpvi_batch_t b, int32_t mode) {
+  if (!b) return fail(MDPVI_EINVAL, "NULL batch");
+  if (mode < -1 || mode > 1) return fail(MDPVI_EINVAL, "mode=%d not in {-1, 0, 1}", mode);
+  b->vi_tile = mode;
+  return MDPVI_OK;
+}
+
+int32_t batch_vi_tile_instances(mdpvi_batch_t b) {
+  if (!b) return -1;
+  if (!batch_vi_tile_on(b)) return 0;
+  int32_t c = 0;
+  for (int32_t t : b->tocc) c += t > 0 ? 1 : 0;
+  return c;
+}
+
 int batch_autotune(mdpvi_batch_t b, int32_t trials, void* hip_stream, int32_t* opt, double* us) {
   if (!b) return fail(MDPVI_EINVAL, "NULL batch");
   if (trials < 1 || trials > 1000) return fail(MDPVI_EINVAL, "trials=%d outside [1, 1000]", trials);
@@ -2170,6 +2265,31 @@ int batch_autotune(mdpvi_batch_t b, int32_t trials, void* hip_stream, int32_t* o
       tune_record_key(batch_tune_key(b, op), best, best_us);
       if (opt) opt[op] = best;
       if (us) us[op] = best_us;
+      if (vi && !b->vt_tiles.empty()) {
+        // the tile form for the instances it covers, the direct form with the
+        // chosen occupancies per thread for the others
+        const int oi = opt_index(best);
+        const int nt = static_cast<int>(b->rtiles_nt[oi].size());
+        const int nvt = static_cast<int>(b->vt_tiles.size());
+        HIP_TRY(mdpvi::launch_batch_arrival_init(b->d_inst, b->d_rtiles[oi], static_cast<int>(b->rtiles[oi].size()),
+                                                 v32, b->d_A[0], b->d_A[1], best, s));
+        std::vector<float> ms(trials);
+        for (int r = -1; r < trials; ++r) {
+          HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_all, b->n, b->d_remaining, b->d_flags, 0, s));
+          HIP_TRY(hipEventRecord(b->ev0, s));
+          HIP_TRY(mdpvi::launch_batch_vi_tile(b->d_inst, b->d_vt_tiles, nvt, b->vt_lds, v32, b->W, b->d_ctl,
+                                              b->d_remaining, 0, 1.0, b->d_A[0], b->d_A[1], s));
+          HIP_TRY(mdpvi::launch_batch_round(b->d_inst, b->d_rtiles_nt[oi], nt, b->rnd_maxK, b->rnd_maxJ, v32, b->W,
+                                            b->d_ctl, b->d_remaining, 0, 1.0, best, b->d_A[0], b->d_A[1], s));
+          HIP_TRY(hipEventRecord(b->ev1, s));
+          HIP_TRY(hipEventSynchronize(b->ev1));
+          if (r >= 0) HIP_TRY(hipEventElapsedTime(&ms[r], b->ev0, b->ev1));
+        }
+        std::sort(ms.begin(), ms.end());
+        const double t = ms[trials / 2] * 1e3;
+        tune_record_key(batch_tune_key(b, 0) + "|tile", t < best_us ? 1 : 0, t);
+        if (us && t < best_us) us[0] = t;
+      }
     }
     return MDPVI_OK;
   };

@@ -27,6 +27,7 @@
 #include "device.hpp"
 #include "kernels.hpp"
 #include "adjoint_impl.hpp"
+#include "tile_vi.hpp"
 #include "policy_impl.hpp"
 #include "sweep_impl.hpp"
 
@@ -289,6 +290,37 @@ __device__ __forceinline__ bool inst_stopped(BatchCtl* c, long long j, double to
   return false;
 }
 
+// The workgroup's part of round j's residual of its instance: the largest
+// (kMax, a NaN wins) or the sum (kSum) of the lanes' acc, added to residual
+// word `lane` of the instance's control block.
+template <ResKind RK>
+__device__ __forceinline__ void round_residual(double acc, BatchCtl* c, long long j, uint32_t lane) {
+  __shared__ double part[kBlock / kWave];
+  if constexpr (RK == ResKind::kMax) {
+    acc = wave_max(acc);
+  } else {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+  }
+  if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = part[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / kWave; ++w) {
+      if constexpr (RK == ResKind::kMax) m = (part[w] > m || part[w] != part[w]) ? part[w] : m;
+      else m += part[w];
+    }
+    unsigned long long* word = &c->res[j % kResSlots][lane][0];
+    if (m != 0.0) {
+      if constexpr (RK == ResKind::kMax)
+        atomicMax(word, static_cast<unsigned long long>(__double_as_longlong(m)));
+      else
+        atomicAdd(reinterpret_cast<double*>(word), m);
+    }
+  }
+}
+
 // The tile's occupancies through the exact-shape backup of (K, J), reduced
 // as the round kernel reduces them.
 template <class Op, int K, int J>
@@ -361,30 +393,79 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
       }
     }
   }
-  __shared__ double part[kBlock / kWave];
-  if constexpr (Op::RK == ResKind::kMax) {
-    acc = wave_max(acc);
-  } else {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-  }
-  if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = acc;
+  round_residual<Op::RK>(acc, c, j, (tile.first / kBlock) % kBatchLanes);
+}
+
+// Value-iteration round in the tile form (tile_vi.hpp) for the instances
+// with I.tocc > 0 (K in 4..5, J <= 3 distinct sizes, tiles of T = 3 low
+// digits): tile.first is the index of one of the instance's (C+1)^(K-3)
+// tiles.  The workgroup stages the tile's values and arrival terms in LDS
+// (dynamic: Al [tocc + 1], Vl [J][tocc]) and backs up its occupancies with
+// the low-digit neighbours from LDS and the high-digit ones from global
+// memory: the per-state arithmetic of the direct round backup, so the same
+// bits.  Placements without room read the -inf block that ends the
+// instance's side arrays.
+template <int K, int J>
+__device__ __forceinline__ double batch_vi_tile_body(const BatchInst& I, uint32_t tb, const float* Vin,
+                                                     float* Vout, const double* Ain, double* Aout,
+                                                     double* Al, float* Vl) {
+  constexpr int T = 3;
+  const Model& M = I.M;
+  const uint32_t occ = static_cast<uint32_t>(I.tocc);
+  const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
+  const uint32_t ns = static_cast<uint32_t>(M.n_states);
+  const uint32_t cls = nocc * 4u;
+  const BufView vin = make_view(Vin, ns * 4u);
+  const BufView vout = make_view(Vout, ns * 4u);
+  const BufView ain = make_view(Ain, (nocc + occ) * 8u);
+  const BufView aout = make_view(Aout, nocc * 8u);
+  TileHigh<K, J, T> H;
+  tile_high_setup<K, J, T>(M, tb, H);
+  tile_stage<J, kBlock>(M, occ, H.o0, vin, ain, Vl, Al);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = part[0];
+  double acc = 0.0;
+  for (uint32_t i = threadIdx.x; i < occ; i += kBlock) {
+    float vs[J], vn[J];
+    double anew;
+    tile_backup<K, J, T, false>(M, H, occ, Vl, Al, vin, ain, i, vs, vn, anew);
 #pragma unroll
-    for (int w = 1; w < kBlock / kWave; ++w) {
-      if constexpr (Op::RK == ResKind::kMax) m = (part[w] > m || part[w] != part[w]) ? part[w] : m;
-      else m += part[w];
+    for (int e = 0; e < J; ++e) {
+      st_f32(vout, vn[e], i * 4u, H.o0 * 4u + e * cls);
+      const double d = fabs(static_cast<double>(vn[e]) - static_cast<double>(vs[e]));
+      acc = (d > acc || d != d) ? d : acc;
     }
-    unsigned long long* word = &c->res[j % kResSlots][(tile.first / kBlock) % kBatchLanes][0];
-    if (m != 0.0) {
-      if constexpr (Op::RK == ResKind::kMax)
-        atomicMax(word, static_cast<unsigned long long>(__double_as_longlong(m)));
-      else
-        atomicAdd(reinterpret_cast<double*>(word), m);
-    }
+    st_f64(aout, anew, i * 8u, H.o0 * 8u);
   }
+  return acc;
+}
+
+__global__ __launch_bounds__(kBlock) void batch_vi_tile_kernel(const BatchInst* __restrict__ insts,
+                                                                const Tile* __restrict__ tiles,
+                                                                float* __restrict__ V, float* __restrict__ W,
+                                                                BatchCtl* __restrict__ ctl, int* remaining,
+                                                                long long j, double tol, double* A0, double* A1) {
+  extern __shared__ double tile_lds[];
+  const Tile tile = tiles[blockIdx.x];
+  const BatchInst& I = insts[tile.inst];
+  const Model& M = I.M;
+  BatchCtl* c = ctl + tile.inst;
+  if (inst_stopped<ResKind::kMax>(c, j, tol, remaining, tile.first == 0)) return;
+  const float* Vin = ((j & 1) ? W : V) + I.offset;
+  float* Vout = ((j & 1) ? V : W) + I.offset;
+  const double* Ain = ((j & 1) ? A1 : A0) + I.aoff;
+  double* Aout = ((j & 1) ? A0 : A1) + I.aoff;
+  double* Al = tile_lds;
+  float* Vl = reinterpret_cast<float*>(tile_lds + I.tocc + 1);
+  double acc = 0.0;
+  switch (M.K * 4 + M.J) {
+#define MDPVI_TILE_CASE(K_, J_) \
+  case K_ * 4 + J_: acc = batch_vi_tile_body<K_, J_>(I, tile.first, Vin, Vout, Ain, Aout, Al, Vl); break;
+    MDPVI_TILE_CASE(4, 1) MDPVI_TILE_CASE(4, 2) MDPVI_TILE_CASE(4, 3)
+    MDPVI_TILE_CASE(5, 1) MDPVI_TILE_CASE(5, 2) MDPVI_TILE_CASE(5, 3)
+#undef MDPVI_TILE_CASE
+    default: acc = NAN;   // not a tile-form shape: the host never lists such a tile
+  }
+  round_residual<ResKind::kMax>(acc, c, j, tile.first % kBatchLanes);
 }
 
 // Copies the final iterate of instances that stopped after an odd number of
@@ -434,9 +515,12 @@ __global__ __launch_bounds__(kBlock) void batch_arrival_init_kernel(const BatchI
   if (I.aoff < 0) return;
   const Model& M = I.M;
   const uint64_t nocc = static_cast<uint64_t>(M.n_occ);
-  if (tile.first == 0 && threadIdx.x == 0) {
-    A0[I.aoff + nocc] = -INFINITY;
-    A1[I.aoff + nocc] = -INFINITY;
+  if (tile.first == 0) {   // the -inf block: one entry, or tocc for the tile form
+    const uint32_t ns = I.tocc > 0 ? static_cast<uint32_t>(I.tocc) : 1u;
+    for (uint32_t t = threadIdx.x; t < ns; t += kBlock) {
+      A0[I.aoff + nocc + t] = -INFINITY;
+      A1[I.aoff + nocc + t] = -INFINITY;
+    }
   }
   for (int k = 0; k < opt; ++k) {
     const uint64_t o = tile.first + threadIdx.x + static_cast<uint64_t>(k) * kBlock;
@@ -751,6 +835,16 @@ hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_t
                               long long j, double tol, int opt, double* A0, double* A1, hipStream_t s) {
   return launch_round_t<VIOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, nullptr, ctl, remaining, j, tol, opt,
                               A0, A1, s);
+}
+
+hipError_t launch_batch_vi_tile(const BatchInst* insts, const Tile* tiles, int n_tiles, size_t lds, float* V,
+                                float* W, BatchCtl* ctl, int* remaining, long long j, double tol, double* A0,
+                                double* A1, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  if (A0 == nullptr || A1 == nullptr || lds == 0 || lds > kBatchTileLds) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(batch_vi_tile_kernel, dim3(n_tiles), dim3(kBlock), lds, s, insts, tiles, V, W, ctl,
+                     remaining, j, tol, A0, A1);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,

@@ -10,6 +10,7 @@ constexpr int kBatchLanes = 8;        // residual words per instance (round form
 constexpr size_t kLdsBudget = 160 * 1024 - 1024;  // dynamic LDS per workgroup
 constexpr int kBatchExactK = 5;       // host counts up to which the round kernels
                                       // carry exact-shape backups
+constexpr size_t kBatchTileLds = 60 * 1024;   // dynamic LDS of a tile-form round workgroup
 
 struct BatchInst {
   Model M;
@@ -20,11 +21,15 @@ struct BatchInst {
                     // doubles) in the adjoint's line table; -1 when none
   int32_t lds;      // 1: solved LDS-resident by one workgroup
   int32_t ctl;      // index of its round-form control block (-1 if none)
+  int32_t tocc;     // > 0: its value-iteration rounds run in the tile form, with
+                    // tiles of tocc = (C+1)^3 occupancies (its arrival side
+                    // arrays then end in tocc -inf entries); 0: direct form
+  int32_t pad;
 };
 
 struct Tile {
   int32_t inst;
-  uint32_t first;   // first occupancy of the tile
+  uint32_t first;   // first occupancy of the tile (tile form: the tile's index)
 };
 
 struct BatchCtl {

@@ -144,6 +144,13 @@ hipError_t launch_batch_ctl_init(BatchCtl* ctl, const int32_t* list, int n_list,
 hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                               int maxJ, float* V, float* W, BatchCtl* ctl, int* remaining,
                               long long j, double tol, int opt, double* A0, double* A1, hipStream_t s);
+// Value iteration's round in the tile form over tiles {inst, tile index} of
+// instances with tocc > 0 (K in 4..5, J <= 3 distinct sizes); lds: bytes of
+// dynamic LDS, at least (tocc + 1) * 8 + J * tocc * 4 for every listed
+// instance and at most kBatchTileLds.
+hipError_t launch_batch_vi_tile(const BatchInst* insts, const Tile* tiles, int n_tiles, size_t lds, float* V,
+                                float* W, BatchCtl* ctl, int* remaining, long long j, double tol, double* A0,
+                                double* A1, hipStream_t s);
 // The arrival terms of V (the initial iterate) into A0, the -inf entries
 // into A0 and A1, for the instances of the tiles that have side arrays.
 hipError_t launch_batch_arrival_init(const BatchInst* insts, const Tile* tiles, int n_tiles, const float* V,

@@ -138,3 +138,38 @@ def test_batch_round_forms_bit_identical_and_tuned(mdpvi, case):
     assert other.round_forms() == {op: rec[op][0] for op in rec}
     with pytest.raises(mdpvi.MdpviError):
         other.set_round_form("vi", 3)
+
+
+def test_batch_vi_tile_form_bit_identical(mdpvi):
+    """Value iteration's tile form (round-form instances of 4 or 5 hosts and
+    up to 3 distinct sizes, one (C+1)^3 tile per workgroup) gives the direct
+    round form's iterate bit for bit, with the same sweep counts: to
+    convergence from a sub-solution, and stopped after an odd number of
+    sweeps (the iterate then comes back from the second buffer).  The batch
+    mixes covered instances with ones the direct form keeps (a repeated task
+    size) and LDS-resident ones."""
+    import torch
+    insts = list(W.batch(64, seed=3)) + [
+        W.make(4, 12, (1, 1), (0.6, 0.4), 0.1, 0.02, (1.0, 1.3), 0.95),      # repeated sizes: direct
+        W.make(5, 6, (1, 2, 3), (0.9, 0.4, 0.3), 0.1, 0.02, (1.0, 2.4, 3.1), 0.96),
+        W.make(4, 12, (2,), (0.9,), 0.1, 0.02, (2.0,), 0.95, idle_unit_cost=0.05)]   # J = 1, penalty
+    b = mdpvi.Batch(insts)
+    lb = torch.zeros(b.num_states, device="cuda")
+    for i, p in enumerate(insts):
+        lb[b.offsets[i]:b.offsets[i + 1]] = sub_solution(p)
+    outs = {}
+    for mode in (0, 1):
+        b.set_vi_tile(mode)
+        n_tile = b.vi_tile_instances()
+        assert (n_tile > 0) == (mode == 1), (mode, n_tile)
+        V = lb.clone()
+        st, its, res = b.vi_solve(V, tol=1e-6)
+        V7 = lb.clone()
+        with pytest.raises(mdpvi.MdpviError) as e:
+            b.vi_solve(V7, tol=1e-30, max_iter=7)
+        assert e.value.code == mdpvi.ENOCONV
+        outs[mode] = (V.cpu().numpy().view(np.uint32), list(its), V7.cpu().numpy().view(np.uint32))
+        print(f"tile mode {mode}: {n_tile} instances in the tile form, {st['seconds'] * 1e3:.1f} ms", flush=True)
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][2], outs[1][2])
