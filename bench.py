@@ -98,6 +98,7 @@ def batched_vs_per_instance(mdpvi, n: int, tol: float) -> dict:
             "per_instance_seconds": t_single, "per_instance_backups_per_s": backups_single / t_single,
             "speedup": t_single / t_batch, "max_sweeps": max(its),
             "round_kernel_occupancies_per_thread": b.round_forms(),
+            "tile_form_instances": {op: b.tile_form_instances(op) for op in ("vi", "eval")},
             "autotuned_us_per_round": {k: v[1] for k, v in tuned.items()}}
 
 
@@ -314,6 +315,7 @@ def gradient_workloads(mdpvi, n_batch: int, tol: float) -> dict:
                         "gradients_per_s": n_batch / t_batch,
                         "stage_seconds": stages, "evaluation_rounds": pi_rounds,
                         "round_kernel_occupancies_per_thread": b.round_forms(),
+                        "tile_form_instances": {op: b.tile_form_instances(op) for op in ("vi", "eval")},
                         "autotuned_us_per_round": {k: v[1] for k, v in b_tuned.items()},
                         "mean_J_opt_minus_J_greedy": float(np.mean(gaps)),
                         "min_J_opt_minus_J_greedy": float(np.min(gaps))}}

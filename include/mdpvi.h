@@ -375,32 +375,36 @@ int batch_set_round_form(mdpvi_batch_t b, int32_t op, int32_t opt);
  * evaluation and adjoint calls on this batch use.  Errors: MDPVI_EINVAL.   */
 int batch_round_forms(mdpvi_batch_t b, int32_t *opt);
 
-/* Value iteration's round kernels for the batch's round-form instances of 4
- * or 5 hosts and up to 3 classes of distinct sizes (a tuning knob: the
- * same bits either way): mode 1 runs them in the tile form (each workgroup
- * stages one tile of (C+1)^3 occupancies, values and arrival terms, in LDS
- * (at most 60 KB)
- * and reads every neighbour along the three low digits from there), 0 in
- * the direct form with the other round-form instances, -1 automatic (the
- * default: the choice batch_autotune recorded for the batch's instance
- * shapes, else the tile form).  Errors: MDPVI_EINVAL.                        */
-int batch_set_vi_tile(mdpvi_batch_t b, int32_t mode);
+/* Tile form of the round kernels of operation op (0 value iteration, 1 FP64
+ * evaluation) for the batch's instances of 4 or 5 hosts and up to 3 classes
+ * of distinct sizes (a tuning knob: the same bits either way).  Each
+ * workgroup stages one tile of (C+1)^3 occupancies in LDS (at most 60 KB;
+ * value iteration: values and arrival terms of its round-form instances;
+ * evaluation: values of the instances with tiles of at least 216
+ * occupancies, the arrival terms of the actions then coming from FP64 side
+ * arrays) and reads every neighbour along the three low digits from there;
+ * the other instances keep the direct round kernels.  mode 1 on, 0 off, -1
+ * automatic (the default: the choice batch_autotune recorded for the
+ * batch's instance shapes, else on for value iteration and off for
+ * evaluation).  Errors: MDPVI_EINVAL.                                        */
+int batch_set_tile_form(mdpvi_batch_t b, int32_t op, int32_t mode);
 
-/* The number of instances the next vi_solve_batch runs in the tile form
- * (0 when the form is off or covers none); -1 for a NULL batch.            */
-int32_t batch_vi_tile_instances(mdpvi_batch_t b);
+/* The number of instances the next value iteration (op 0) or evaluation
+ * (op 1) call on this batch runs in the tile form (0 when the form is off
+ * or covers none); -1 for a NULL batch or another op.                      */
+int32_t batch_tile_form_instances(mdpvi_batch_t b, int32_t op);
 
 /* Times one round of each operation's round kernel with 1, 2 and 4
  * occupancies per thread over every instance of the batch (trials rounds
  * each, median; zero inputs and the least-loaded policy, in temporary
  * buffers) and records the fastest per operation in the tuning cache, keyed
  * by the architecture and a digest of the instances' (K, C, J, sizes); any
- * batch of the same instance shapes then uses it.  For value iteration it
- * then times the tile form (batch_set_vi_tile) beside the winner and
- * records whether it is faster.  opt[3], us[3] (host, nullable): the
- * choices and their median microseconds per round (us[0]: of the faster of
- * the two value-iteration forms; value iteration is skipped, and its
- * entries left unchanged, when every instance is solved in LDS).
+ * batch of the same instance shapes then uses it.  For value iteration and
+ * evaluation it then times the tile form (batch_set_tile_form) beside the
+ * winner and records whether it is faster.  opt[3], us[3] (host,
+ * nullable): the choices and their median microseconds per round (us[0],
+ * us[1]: of the faster form; value iteration is skipped, and its entries
+ * left unchanged, when every instance is solved in LDS).
  * Synchronous.  Errors: MDPVI_EINVAL, MDPVI_ENOMEM, MDPVI_EDEVICE.          */
 int batch_autotune(mdpvi_batch_t b, int32_t trials, void *hip_stream, int32_t *opt, double *us);
 

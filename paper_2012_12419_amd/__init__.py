@@ -99,8 +99,8 @@ SIGNATURES = {
                                               ctypes.POINTER(Stats), ctypes.POINTER(_c_int64)]),
     "batch_set_round_form": (ctypes.c_int, [_vp, _c_int32, _c_int32]),
     "batch_round_forms": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int32)]),
-    "batch_set_vi_tile": (ctypes.c_int, [_vp, _c_int32]),
-    "batch_vi_tile_instances": (_c_int32, [_vp]),
+    "batch_set_tile_form": (ctypes.c_int, [_vp, _c_int32, _c_int32]),
+    "batch_tile_form_instances": (_c_int32, [_vp, _c_int32]),
     "batch_autotune": (ctypes.c_int, [_vp, _c_int32, _vp, ctypes.POINTER(_c_int32),
                                       ctypes.POINTER(_c_double)]),
     "mdp_set_timing": (ctypes.c_int, [_vp, _c_int32]),
@@ -415,14 +415,14 @@ class Batch:
         _check(load().batch_round_forms(self._h, out))
         return {k: int(out[v]) for k, v in self.ROUND_OPS.items()}
 
-    def set_vi_tile(self, mode: int = -1):
-        """Value iteration's tile form for the instances it covers: 1 on, 0
-        off, -1 automatic."""
-        _check(load().batch_set_vi_tile(self._h, int(mode)))
+    def set_tile_form(self, op: str, mode: int = -1):
+        """Tile form of the round kernels of op ("vi" or "eval") for the
+        instances it covers: 1 on, 0 off, -1 automatic."""
+        _check(load().batch_set_tile_form(self._h, self.ROUND_OPS[op], int(mode)))
 
-    def vi_tile_instances(self) -> int:
-        """Instances the next vi_solve runs in the tile form."""
-        return int(load().batch_vi_tile_instances(self._h))
+    def tile_form_instances(self, op: str) -> int:
+        """Instances the next call of op ("vi" or "eval") runs in the tile form."""
+        return int(load().batch_tile_form_instances(self._h, self.ROUND_OPS[op]))
 
     def autotune(self, trials: int = 5, stream=None) -> dict:
         """Time the round kernels with 1, 2 and 4 occupancies per thread and

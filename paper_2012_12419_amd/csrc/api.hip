@@ -669,7 +669,18 @@ struct mdpvi_batch {
   mdpvi::Tile* d_rtiles_nt[3] = {nullptr, nullptr, nullptr};
   mdpvi::Tile* d_vact[2] = {nullptr, nullptr};   // active-tile lists of the tile form
   size_t vt_lds = 0;                     // dynamic LDS of the tile-form rounds
-  int vi_tile = -1;                      // tile form: -1 automatic, 0 off, 1 on
+  // FP64 evaluation's tile form: tiles of the instances it covers (eocc > 0),
+  // the direct tiles of the others, and its arrival side arrays
+  std::vector<int32_t> eocc;             // per instance: (C+1)^3, or 0
+  std::vector<mdpvi::Tile> et_tiles, rtiles_all_nt[3];
+  mdpvi::Tile* d_et_tiles = nullptr;
+  mdpvi::Tile* d_rtiles_all_nt[3] = {nullptr, nullptr, nullptr};
+  mdpvi::Tile* d_eact[2] = {nullptr, nullptr};
+  size_t et_lds = 0;
+  double* d_E[2] = {nullptr, nullptr};
+  int64_t e_total = 0;                   // their length: sum of n_occ
+  int tile_mode[2] = {-1, -1};           // tile form of value iteration and evaluation:
+                                         // -1 automatic, 0 off, 1 on
   int round_opt[3] = {0, 0, 0};          // per operation (value iteration, evaluation, adjoint):
                                          // occupancies per thread, 0 automatic
   int lds_maxK = 1, lds_maxJ = 1, rnd_maxK = 1, rnd_maxJ = 1, maxK = 1, maxJ = 1;
@@ -1484,14 +1495,34 @@ int batch_opt(const mdpvi_batch* b, int op) {
 
 int opt_index(int opt) { return opt == 1 ? 0 : opt == 2 ? 1 : 2; }
 
-// Whether value iteration's rounds run the tile form for the instances it
-// covers: the mode set on the batch, else the choice batch_autotune recorded
-// for its shapes, else on.
-bool batch_vi_tile_on(const mdpvi_batch* b) {
-  if (b->vt_tiles.empty()) return false;
-  if (b->vi_tile >= 0) return b->vi_tile == 1;
-  const int cached = tune_lookup_key(batch_tune_key(b, 0) + "|tile");
-  return cached != 0;
+// Whether the rounds of operation op (0 value iteration, 1 evaluation) run
+// the tile form for the instances it covers: the mode set on the batch,
+// else the choice batch_autotune recorded for its shapes, else on for value
+// iteration and off for evaluation (on the 256-instance gradient batch the
+// tile form takes value iteration from 76 to 49 ms but evaluation to
+// tolerance from 121 to 148 ms).
+bool batch_tile_on(const mdpvi_batch* b, int op) {
+  if ((op == 0 ? b->vt_tiles : b->et_tiles).empty()) return false;
+  if (b->tile_mode[op] >= 0) return b->tile_mode[op] == 1;
+  const int cached = tune_lookup_key(batch_tune_key(b, op) + "|tile");
+  return cached == -2 ? op == 0 : cached != 0;
+}
+
+// The evaluation rounds' tile lists: direct tiles with opt occupancies per
+// thread (t, n) and tile-form tiles (t2, n2; none when the form is off).
+struct EvalLists {
+  const mdpvi::Tile* t;
+  int n;
+  const mdpvi::Tile* t2;
+  int n2;
+};
+
+EvalLists eval_lists(const mdpvi_batch* b, int opt) {
+  const int oi = opt_index(opt);
+  if (batch_tile_on(b, 1))
+    return {b->d_rtiles_all_nt[oi], static_cast<int>(b->rtiles_all_nt[oi].size()), b->d_et_tiles,
+            static_cast<int>(b->et_tiles.size())};
+  return {b->d_rtiles_all[oi], static_cast<int>(b->rtiles_all[oi].size()), nullptr, 0};
 }
 
 int ensure_batch_device(mdpvi_batch* b) {
@@ -1512,7 +1543,8 @@ int ensure_batch_device(mdpvi_batch* b) {
     inst[i].loff = -1;
     inst[i].lds = 0;
     inst[i].tocc = b->tocc[i];
-    inst[i].pad = 0;
+    inst[i].eocc = b->eocc[i];
+    inst[i].eoff = -1;
     inst[i].ctl = -1;
   }
   for (int32_t i : b->lds_list) inst[i].lds = 1;
@@ -1520,6 +1552,13 @@ int ensure_batch_device(mdpvi_batch* b) {
   for (int32_t i : b->round_list) {
     inst[i].aoff = b->a_total;
     b->a_total += b->models[i].n_occ + std::max<int64_t>(1, b->tocc[i]);
+  }
+  b->e_total = 0;
+  for (int i = 0; i < n; ++i) {
+    if (b->eocc[i] > 0) {
+      inst[i].eoff = b->e_total;
+      b->e_total += b->models[i].n_occ;
+    }
   }
   // line tables for the instances whose adjoint rounds take the exact backup
   b->l_total = 0;
@@ -1557,6 +1596,16 @@ int ensure_batch_device(mdpvi_batch* b) {
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_ctl), std::max(n_ctl, 1) * sizeof(mdpvi::BatchCtl)))) return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_remaining), 3 * sizeof(int)))) return rc;
   if ((rc = dalloc(reinterpret_cast<void**>(&b->d_vt_tiles), b->vt_tiles.size() * sizeof(mdpvi::Tile)))) return rc;
+  if ((rc = dalloc(reinterpret_cast<void**>(&b->d_et_tiles), b->et_tiles.size() * sizeof(mdpvi::Tile)))) return rc;
+  for (int a = 0; a < 2; ++a) {
+    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_eact[a]), std::max<size_t>(b->et_tiles.size(), 1) * sizeof(mdpvi::Tile))))
+      return rc;
+    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_E[a]), b->e_total * sizeof(double)))) return rc;
+  }
+  for (int oi = 0; oi < 3; ++oi)
+    if ((rc = dalloc(reinterpret_cast<void**>(&b->d_rtiles_all_nt[oi]),
+                     b->rtiles_all_nt[oi].size() * sizeof(mdpvi::Tile))))
+      return rc;
   for (int a = 0; a < 2; ++a)
     if ((rc = dalloc(reinterpret_cast<void**>(&b->d_vact[a]), std::max<size_t>(b->vt_tiles.size(), 1) * sizeof(mdpvi::Tile))))
       return rc;
@@ -1613,6 +1662,13 @@ int ensure_batch_device(mdpvi_batch* b) {
   if (!b->vt_tiles.empty())
     HIP_TRY(hipMemcpy(b->d_vt_tiles, b->vt_tiles.data(), b->vt_tiles.size() * sizeof(mdpvi::Tile),
                       hipMemcpyHostToDevice));
+  if (!b->et_tiles.empty())
+    HIP_TRY(hipMemcpy(b->d_et_tiles, b->et_tiles.data(), b->et_tiles.size() * sizeof(mdpvi::Tile),
+                      hipMemcpyHostToDevice));
+  for (int oi = 0; oi < 3; ++oi)
+    if (!b->rtiles_all_nt[oi].empty())
+      HIP_TRY(hipMemcpy(b->d_rtiles_all_nt[oi], b->rtiles_all_nt[oi].data(),
+                        b->rtiles_all_nt[oi].size() * sizeof(mdpvi::Tile), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_all, b->all_list.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_tile_begin, b->tile_begin.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
@@ -1727,6 +1783,31 @@ int mdp_build_batch(const mdpvi_params* p, int32_t n, mdpvi_batch_t* out) {
       }
     }
   }
+  // FP64 evaluation's tile form: instances of 4 or 5 hosts and up to 3
+  // classes of distinct sizes whose (C+1)^3-occupancy tile has at least 216
+  // occupancies (one per lane of most of the workgroup) and fits the LDS
+  b->eocc.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    const Model& M = b->models[i];
+    const int64_t occ = static_cast<int64_t>(M.R) * M.R * M.R;
+    const bool views = M.n_states < (int64_t{1} << 28);
+    if ((M.K == 4 || M.K == 5) && M.J <= 3 && M.n_sizes == M.J && views && occ >= 216 &&
+        occ * 8 * M.J <= static_cast<int64_t>(mdpvi::kBatchTileLds))
+      b->eocc[i] = static_cast<int32_t>(occ);
+  }
+  for (int i = 0; i < n; ++i) {
+    const Model& M = b->models[i];
+    if (b->eocc[i] > 0) {
+      const uint32_t nt = static_cast<uint32_t>(M.n_occ / b->eocc[i]);
+      for (uint32_t t = 0; t < nt; ++t) b->et_tiles.push_back({i, t});
+      b->et_lds = std::max(b->et_lds, static_cast<size_t>(b->eocc[i]) * 8 * M.J);
+    } else {
+      for (int oi = 0; oi < 3; ++oi) {
+        const uint32_t per = static_cast<uint32_t>(mdpvi::kBlock) << oi;
+        for (uint32_t t = 0; t < static_cast<uint32_t>(M.n_occ); t += per) b->rtiles_all_nt[oi].push_back({i, t});
+      }
+    }
+  }
   std::sort(cost.begin(), cost.end(), [](auto& x, auto& y) { return x.first > y.first; });
   for (auto& c : cost) b->lds_list.push_back(c.second);
   b->lds_bytes = static_cast<size_t>(2 * max_lds_n) * sizeof(float);
@@ -1758,6 +1839,12 @@ void mdp_free_batch(mdpvi_batch_t b) {
   (void)hipFree(b->d_A[1]);
   (void)hipFree(b->d_lines);
   (void)hipFree(b->d_vt_tiles);
+  (void)hipFree(b->d_et_tiles);
+  for (int a = 0; a < 2; ++a) {
+    (void)hipFree(b->d_eact[a]);
+    (void)hipFree(b->d_E[a]);
+  }
+  for (int oi = 0; oi < 3; ++oi) (void)hipFree(b->d_rtiles_all_nt[oi]);
   (void)hipFree(b->d_vact[0]);
   (void)hipFree(b->d_vact[1]);
   for (int oi = 0; oi < 3; ++oi) (void)hipFree(b->d_rtiles_nt[oi]);
@@ -1825,7 +1912,7 @@ int vi_solve_batch(mdpvi_batch_t b, float* V, double tol, int64_t max_iter, void
     HIP_TRY(mdpvi::launch_batch_arrival_init(b->d_inst, b->d_rtiles[oi], static_cast<int>(b->rtiles[oi].size()), V,
                                              b->d_A[0], b->d_A[1], opt, s));
     // the tile form's instances, and the direct form's (the others, or all)
-    const bool tile = batch_vi_tile_on(b);
+    const bool tile = batch_tile_on(b, 0);
     const mdpvi::Tile* vtiles = tile ? b->d_vt_tiles : nullptr;
     int nvt = tile ? static_cast<int>(b->vt_tiles.size()) : 0;
     const mdpvi::Tile* tiles = tile ? b->d_rtiles_nt[oi] : b->d_rtiles[oi];
@@ -1920,36 +2007,46 @@ int batch_check_policy(mdpvi_batch* b, const uint8_t* pi, hipStream_t s, int* ba
 // With `active` (device int[n], nullable), only the instances with
 // active[i] != 0 (n_active of them) are swept; the others keep their values
 // and report 0 sweeps.
+// The round loop over every instance (or the active ones): round(j, tiles,
+// n, tiles2, n2) issues round j over the direct-form tiles and the
+// tile-form tiles (tiles2: the evaluation's, or none), which are compacted
+// to the instances still running after each chunk.
 template <typename Round, typename Finish>
-int batch_all_rounds(mdpvi_batch* b, int opt, double tol, int64_t max_iter, hipStream_t s, mdpvi_stats* st,
-                     int64_t* iterations, double* residuals, double bytes_per_state, Round round,
-                     Finish finish, const int* active = nullptr, int n_active = 0) {
+int batch_all_rounds(mdpvi_batch* b, const mdpvi::Tile* tiles, int nt, const mdpvi::Tile* tiles2, int nt2,
+                     double tol, int64_t max_iter, hipStream_t s, mdpvi_stats* st, int64_t* iterations,
+                     double* residuals, double bytes_per_state, Round round, Finish finish,
+                     const int* active = nullptr, int n_active = 0) {
   int64_t issued = 0, chunk = 8;
-  const mdpvi::Tile* tiles = b->d_rtiles_all[opt_index(opt)];
-  int nt = static_cast<int>(b->rtiles_all[opt_index(opt)].size()), cur = 0;
+  int cur = 0;
   if (active) {
     HIP_TRY(mdpvi::launch_batch_ctl_activate(b->d_ctl, active, b->n, b->d_remaining, n_active, s));
     HIP_TRY(mdpvi::launch_batch_compact(tiles, nt, b->d_ctl, b->d_act[cur], b->d_remaining + 1, s));
-    HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(mdpvi::launch_batch_compact(tiles2, nt2, b->d_ctl, b->d_eact[cur], b->d_remaining + 2, s));
+    HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     tiles = b->d_act[cur];
     nt = b->h_remaining[1];
+    tiles2 = b->d_eact[cur];
+    nt2 = b->h_remaining[2];
     cur ^= 1;
   } else {
     HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_all, b->n, b->d_remaining, b->d_flags, 0, s));
   }
   HIP_TRY(hipEventRecord(b->ev0, s));
-  while (issued < max_iter && nt > 0) {
+  while (issued < max_iter && nt + nt2 > 0) {
     const int64_t m = std::min<int64_t>(chunk, max_iter - issued);
-    for (int64_t k = 0; k < m; ++k) HIP_TRY(round(issued + k, tiles, nt));
+    for (int64_t k = 0; k < m; ++k) HIP_TRY(round(issued + k, tiles, nt, tiles2, nt2));
     issued += m;
     // drop the tiles of instances that have stopped from the next chunk
     HIP_TRY(mdpvi::launch_batch_compact(tiles, nt, b->d_ctl, b->d_act[cur], b->d_remaining + 1, s));
-    HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(mdpvi::launch_batch_compact(tiles2, nt2, b->d_ctl, b->d_eact[cur], b->d_remaining + 2, s));
+    HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (b->h_remaining[0] <= 0) break;
     tiles = b->d_act[cur];
     nt = b->h_remaining[1];
+    tiles2 = b->d_eact[cur];
+    nt2 = b->h_remaining[2];
     cur ^= 1;
     if (chunk < kMaxChunk) chunk *= 2;
   }
@@ -2045,9 +2142,14 @@ int policy_eval_batch(mdpvi_batch_t b, const uint8_t* pi, double* V, double tol,
   if (bad >= 0) return fail(MDPVI_EINVAL, "instance %d: policy has an infeasible action", bad);
   double* W = static_cast<double*>(b->W2);
   const int opt = batch_opt(b, 1);
+  EvalLists L = eval_lists(b, opt);
+  if (L.n2) HIP_TRY(mdpvi::launch_batch_eval_arrival_init(b->d_inst, L.t2, L.n2, V, b->d_E[0], s));
   return batch_all_rounds(
-      b, opt, tol, max_iter, s, st, iterations, residuals, 17.0,
-      [&](long long j, const mdpvi::Tile* tiles, int n) {
+      b, L.t, L.n, L.t2, L.n2, tol, max_iter, s, st, iterations, residuals, 17.0,
+      [&](long long j, const mdpvi::Tile* tiles, int n, const mdpvi::Tile* tiles2, int n2) {
+        const hipError_t e = mdpvi::launch_batch_eval_tile(b->d_inst, tiles2, n2, b->et_lds, pi, V, W, b->d_ctl,
+                                                           b->d_remaining, j, tol, b->d_E[0], b->d_E[1], s);
+        if (e != hipSuccess) return e;
         return mdpvi::launch_batch_eval_round(b->d_inst, tiles, n, b->maxK, b->maxJ, pi, V, W, b->d_ctl,
                                               b->d_remaining, j, tol, opt, s);
       },
@@ -2077,6 +2179,7 @@ int policy_iteration_batch(mdpvi_batch_t b, uint8_t* pi, double* V, double eval_
   if (bad >= 0) return fail(MDPVI_EINVAL, "instance %d: policy has an infeasible action", bad);
   double* W = static_cast<double*>(b->W2);
   const int opt = batch_opt(b, 1);
+  const EvalLists L = eval_lists(b, opt);
   const int n = b->n;
   const auto t0 = std::chrono::steady_clock::now();
   std::vector<int64_t> rr(n, 0);
@@ -2090,9 +2193,13 @@ int policy_iteration_batch(mdpvi_batch_t b, uint8_t* pi, double* V, double eval_
     for (int i = 0; i < n; ++i)
       if (b->h_active[i]) ++rr[i];
     mdpvi_stats e{};
+    if (L.n2) HIP_TRY(mdpvi::launch_batch_eval_arrival_init(b->d_inst, L.t2, L.n2, V, b->d_E[0], s));
     rc = batch_all_rounds(
-        b, opt, eval_tol, eval_max_iter, s, &e, nullptr, nullptr, 17.0,
-        [&](long long j, const mdpvi::Tile* tiles, int nt) {
+        b, L.t, L.n, L.t2, L.n2, eval_tol, eval_max_iter, s, &e, nullptr, nullptr, 17.0,
+        [&](long long j, const mdpvi::Tile* tiles, int nt, const mdpvi::Tile* tiles2, int nt2) {
+          const hipError_t e = mdpvi::launch_batch_eval_tile(b->d_inst, tiles2, nt2, b->et_lds, pi, V, W, b->d_ctl,
+                                                             b->d_remaining, j, eval_tol, b->d_E[0], b->d_E[1], s);
+          if (e != hipSuccess) return e;
           return mdpvi::launch_batch_eval_round(b->d_inst, tiles, nt, b->maxK, b->maxJ, pi, V, W, b->d_ctl,
                                                 b->d_remaining, j, eval_tol, opt, s);
         },
@@ -2142,8 +2249,9 @@ int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t* pi, const double* V_pi, flo
   const int nt = static_cast<int>(b->tiles_all.size());
   const int opt = batch_opt(b, 2);
   rc = batch_all_rounds(
-      b, opt, tol, max_iter, s, st, iterations, nullptr, 9.0,
-      [&](long long j, const mdpvi::Tile* tiles, int n) {
+      b, b->d_rtiles_all[opt_index(opt)], static_cast<int>(b->rtiles_all[opt_index(opt)].size()), nullptr, 0, tol,
+      max_iter, s, st, iterations, nullptr, 9.0,
+      [&](long long j, const mdpvi::Tile* tiles, int n, const mdpvi::Tile*, int) {
         return mdpvi::launch_batch_adjoint_round(b->d_inst, tiles, n, b->maxK, b->maxJ, pi, w, b->W,
                                                  b->d_ctl, b->d_remaining, j, tol, opt, b->d_lines, s);
       },
@@ -2182,18 +2290,19 @@ int batch_round_forms(mdpvi_batch_t b, int32_t* opt) {
   return MDPVI_OK;
 }
 
-int batch_set_vi_tile(mdpvi_batch_t b, int32_t mode) {
+int batch_set_tile_form(mdpvi_batch_t b, int32_t op, int32_t mode) {
   if (!b) return fail(MDPVI_EINVAL, "NULL batch");
+  if (op < 0 || op > 1) return fail(MDPVI_EINVAL, "operation %d outside 0..1", op);
   if (mode < -1 || mode > 1) return fail(MDPVI_EINVAL, "mode=%d not in {-1, 0, 1}", mode);
-  b->vi_tile = mode;
+  b->tile_mode[op] = mode;
   return MDPVI_OK;
 }
 
-int32_t batch_vi_tile_instances(mdpvi_batch_t b) {
-  if (!b) return -1;
-  if (!batch_vi_tile_on(b)) return 0;
+int32_t batch_tile_form_instances(mdpvi_batch_t b, int32_t op) {
+  if (!b || op < 0 || op > 1) return -1;
+  if (!batch_tile_on(b, op)) return 0;
   int32_t c = 0;
-  for (int32_t t : b->tocc) c += t > 0 ? 1 : 0;
+  for (int32_t t : (op == 0 ? b->tocc : b->eocc)) c += t > 0 ? 1 : 0;
   return c;
 }
 
@@ -2289,6 +2398,29 @@ int batch_autotune(mdpvi_batch_t b, int32_t trials, void* hip_stream, int32_t* o
         const double t = ms[trials / 2] * 1e3;
         tune_record_key(batch_tune_key(b, 0) + "|tile", t < best_us ? 1 : 0, t);
         if (us && t < best_us) us[0] = t;
+      }
+      if (op == 1 && !b->et_tiles.empty()) {
+        // the evaluation's tile form beside the winner's direct tiles
+        const int oi = opt_index(best);
+        const int nt = static_cast<int>(b->rtiles_all_nt[oi].size());
+        const int net = static_cast<int>(b->et_tiles.size());
+        HIP_TRY(mdpvi::launch_batch_eval_arrival_init(b->d_inst, b->d_et_tiles, net, v64, b->d_E[0], s));
+        std::vector<float> ms(trials);
+        for (int r = -1; r < trials; ++r) {
+          HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_all, b->n, b->d_remaining, b->d_flags, 0, s));
+          HIP_TRY(hipEventRecord(b->ev0, s));
+          HIP_TRY(mdpvi::launch_batch_eval_tile(b->d_inst, b->d_et_tiles, net, b->et_lds, pol, v64, w64, b->d_ctl,
+                                                b->d_remaining, 0, 1.0, b->d_E[0], b->d_E[1], s));
+          HIP_TRY(mdpvi::launch_batch_eval_round(b->d_inst, b->d_rtiles_all_nt[oi], nt, b->maxK, b->maxJ, pol, v64,
+                                                 w64, b->d_ctl, b->d_remaining, 0, 1.0, best, s));
+          HIP_TRY(hipEventRecord(b->ev1, s));
+          HIP_TRY(hipEventSynchronize(b->ev1));
+          if (r >= 0) HIP_TRY(hipEventElapsedTime(&ms[r], b->ev0, b->ev1));
+        }
+        std::sort(ms.begin(), ms.end());
+        const double t = ms[trials / 2] * 1e3;
+        tune_record_key(batch_tune_key(b, 1) + "|tile", t < best_us ? 1 : 0, t);
+        if (us && t < best_us) us[1] = t;
       }
     }
     return MDPVI_OK;

@@ -27,6 +27,7 @@
 #include "device.hpp"
 #include "kernels.hpp"
 #include "adjoint_impl.hpp"
+#include "tile_eval.hpp"
 #include "tile_vi.hpp"
 #include "policy_impl.hpp"
 #include "sweep_impl.hpp"
@@ -468,6 +469,66 @@ __global__ __launch_bounds__(kBlock) void batch_vi_tile_kernel(const BatchInst* 
   round_residual<ResKind::kMax>(acc, c, j, tile.first % kBatchLanes);
 }
 
+// FP64 evaluation round in the tile form (tile_eval.hpp) for the instances
+// with I.eocc > 0 (K in 4..5, J <= 3 distinct sizes, tiles of T = 3 low
+// digits): tile.first is the index of one of the instance's tiles.  The
+// arrival terms of the policy's actions come from the instance's FP64 side
+// arrays (E0/E1 + eoff, ping-pong with the values), written by the previous
+// round or by batch_eval_arrival_init_kernel: the same bits as the direct
+// round backup.
+__global__ __launch_bounds__(kBlock) void batch_eval_tile_kernel(const BatchInst* __restrict__ insts,
+                                                                  const Tile* __restrict__ tiles,
+                                                                  const uint8_t* __restrict__ pi,
+                                                                  double* __restrict__ V, double* __restrict__ W,
+                                                                  BatchCtl* __restrict__ ctl, int* remaining,
+                                                                  long long j, double tol, double* E0, double* E1) {
+  extern __shared__ double tile_lds[];
+  const Tile tile = tiles[blockIdx.x];
+  const BatchInst& I = insts[tile.inst];
+  const Model& M = I.M;
+  BatchCtl* c = ctl + tile.inst;
+  if (inst_stopped<ResKind::kMax>(c, j, tol, remaining, tile.first == 0)) return;
+  const uint32_t nocc = static_cast<uint32_t>(M.n_occ);
+  const uint32_t ns = static_cast<uint32_t>(M.n_states);
+  const BufView pv = make_view(pi + I.offset, ns);
+  const BufView vin = make_view(((j & 1) ? W : V) + I.offset, ns * 8u);
+  const BufView vout = make_view(((j & 1) ? V : W) + I.offset, ns * 8u);
+  const BufView ain = make_view(((j & 1) ? E1 : E0) + I.eoff, nocc * 8u);
+  const BufView aout = make_view(((j & 1) ? E0 : E1) + I.eoff, nocc * 8u);
+  const uint32_t occ = static_cast<uint32_t>(I.eocc);
+  double acc = 0.0;
+  switch (M.K * 4 + M.J) {
+#define MDPVI_TILE_CASE(K_, J_) \
+  case K_ * 4 + J_: acc = eval_tile_block<K_, J_, 3, kBlock>(M, tile.first, occ, pv, vin, vout, ain, aout, tile_lds, 0.0); break;
+    MDPVI_TILE_CASE(4, 1) MDPVI_TILE_CASE(4, 2) MDPVI_TILE_CASE(4, 3)
+    MDPVI_TILE_CASE(5, 1) MDPVI_TILE_CASE(5, 2) MDPVI_TILE_CASE(5, 3)
+#undef MDPVI_TILE_CASE
+    default: acc = NAN;   // not a tile-form shape: the host never lists such a tile
+  }
+  round_residual<ResKind::kMax>(acc, c, j, tile.first % kBatchLanes);
+}
+
+// A(o) = sum_e lambda_e/Lam V(o, e) (the FMA chain of the evaluation
+// backups) of the FP64 iterate V into E0, for the occupancies of the
+// evaluation tiles {inst, tile index} (eocc each).
+__global__ __launch_bounds__(kBlock) void batch_eval_arrival_init_kernel(const BatchInst* __restrict__ insts,
+                                                                          const Tile* __restrict__ tiles,
+                                                                          const double* __restrict__ V,
+                                                                          double* __restrict__ E0) {
+  const Tile tile = tiles[blockIdx.x];
+  const BatchInst& I = insts[tile.inst];
+  if (I.eoff < 0 || I.eocc <= 0) return;
+  const Model& M = I.M;
+  const uint64_t nocc = static_cast<uint64_t>(M.n_occ);
+  const uint64_t o0 = static_cast<uint64_t>(tile.first) * static_cast<uint64_t>(I.eocc);
+  for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(I.eocc); i += kBlock) {
+    const uint64_t o = o0 + i;
+    double a = 0.0;
+    for (int e = 0; e < M.J; ++e) a = fma(M.p[e], V[I.offset + o + static_cast<uint64_t>(e) * nocc], a);
+    E0[I.eoff + o] = a;
+  }
+}
+
 // Copies the final iterate of instances that stopped after an odd number of
 // sweeps (it lives in W) back to V, and reports iterations and residuals.
 template <typename T, ResKind RK>
@@ -844,6 +905,23 @@ hipError_t launch_batch_vi_tile(const BatchInst* insts, const Tile* tiles, int n
   if (A0 == nullptr || A1 == nullptr || lds == 0 || lds > kBatchTileLds) return hipErrorInvalidValue;
   hipLaunchKernelGGL(batch_vi_tile_kernel, dim3(n_tiles), dim3(kBlock), lds, s, insts, tiles, V, W, ctl,
                      remaining, j, tol, A0, A1);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_eval_tile(const BatchInst* insts, const Tile* tiles, int n_tiles, size_t lds,
+                                  const uint8_t* pi, double* V, double* W, BatchCtl* ctl, int* remaining,
+                                  long long j, double tol, double* E0, double* E1, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  if (E0 == nullptr || E1 == nullptr || lds == 0 || lds > kBatchTileLds) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(batch_eval_tile_kernel, dim3(n_tiles), dim3(kBlock), lds, s, insts, tiles, pi, V, W, ctl,
+                     remaining, j, tol, E0, E1);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_eval_arrival_init(const BatchInst* insts, const Tile* tiles, int n_tiles, const double* V,
+                                          double* E0, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_eval_arrival_init_kernel, dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles, V, E0);
   return hipGetLastError();
 }
 

@@ -19,12 +19,15 @@ struct BatchInst {
                     // value-iteration side arrays; -1 when it has none
   int64_t loff;     // first entry of its reset-line sums (K J n_occ / (C+1)
                     // doubles) in the adjoint's line table; -1 when none
+  int64_t eoff;     // first entry of its FP64 arrival terms (n_occ doubles) in
+                    // the evaluation's side arrays; -1 when none
   int32_t lds;      // 1: solved LDS-resident by one workgroup
   int32_t ctl;      // index of its round-form control block (-1 if none)
   int32_t tocc;     // > 0: its value-iteration rounds run in the tile form, with
                     // tiles of tocc = (C+1)^3 occupancies (its arrival side
                     // arrays then end in tocc -inf entries); 0: direct form
-  int32_t pad;
+  int32_t eocc;     // > 0: its evaluation rounds run in the tile form, tiles of
+                    // eocc = (C+1)^3 occupancies; 0: direct form
 };
 
 struct Tile {

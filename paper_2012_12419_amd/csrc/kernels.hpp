@@ -151,6 +151,16 @@ hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_t
 hipError_t launch_batch_vi_tile(const BatchInst* insts, const Tile* tiles, int n_tiles, size_t lds, float* V,
                                 float* W, BatchCtl* ctl, int* remaining, long long j, double tol, double* A0,
                                 double* A1, hipStream_t s);
+// FP64 evaluation's round in the tile form over tiles {inst, tile index} of
+// instances with eocc > 0; E0/E1: the evaluation's arrival side arrays
+// (ping-pong like V/W, E0 initialised by launch_batch_eval_arrival_init);
+// lds: bytes of dynamic LDS, at least J * eocc * 8 for every listed
+// instance and at most kBatchTileLds.
+hipError_t launch_batch_eval_tile(const BatchInst* insts, const Tile* tiles, int n_tiles, size_t lds,
+                                  const uint8_t* pi, double* V, double* W, BatchCtl* ctl, int* remaining,
+                                  long long j, double tol, double* E0, double* E1, hipStream_t s);
+hipError_t launch_batch_eval_arrival_init(const BatchInst* insts, const Tile* tiles, int n_tiles, const double* V,
+                                          double* E0, hipStream_t s);
 // The arrival terms of V (the initial iterate) into A0, the -inf entries
 // into A0 and A1, for the instances of the tiles that have side arrays.
 hipError_t launch_batch_arrival_init(const BatchInst* insts, const Tile* tiles, int n_tiles, const float* V,

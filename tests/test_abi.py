@@ -183,11 +183,14 @@ def test_batch_round_form_choice_on_the_host():
         lib.mdp_free_batch(h)
 
 
-def test_batch_vi_tile_choice_on_the_host():
-    """batch_set_vi_tile validates its mode; the tile form covers the
-    round-form instances (more states than two FP32 copies in 159 KB of LDS
-    hold) of 4 or 5 hosts and up to 3 distinct sizes whose (C+1)^3 tile of
-    values and arrival terms fits 60 KB, and is on unless switched off."""
+def test_batch_tile_form_choice_on_the_host():
+    """batch_set_tile_form validates the operation and the mode.  Value
+    iteration's tile form covers the round-form instances (more states than
+    two FP32 copies in 159 KB of LDS hold) of 4 or 5 hosts and up to 3
+    distinct sizes whose (C+1)^3 tile of values and arrival terms fits 60 KB;
+    evaluation's covers the instances of 4 or 5 hosts and up to 3 distinct
+    sizes whose tile has 216 or more occupancies and whose FP64 values fit
+    60 KB.  Unless set, value iteration's is on and evaluation's off."""
     import workloads as W
     lib = mdpvi.load()
     insts = W.batch(40, seed=3)
@@ -198,23 +201,32 @@ def test_batch_vi_tile_choice_on_the_host():
                                       p.reject_cost, p.idle_unit_cost)
         keep.append(k)
     lds_states = (160 * 1024 - 1024) // 8
-    expect = 0
+    expect = [0, 0]
     for p in insts:
         R = p.C + 1
-        if (p.num_states > lds_states and p.K in (4, 5) and p.J <= 3 and len(set(p.size)) == p.J
-                and (R ** 3 + 1) * 8 + R ** 3 * 4 * p.J <= 60 * 1024):
-            expect += 1
-    assert expect > 0
+        shape = p.K in (4, 5) and p.J <= 3 and len(set(p.size)) == p.J
+        if shape and p.num_states > lds_states and (R ** 3 + 1) * 8 + R ** 3 * 4 * p.J <= 60 * 1024:
+            expect[0] += 1
+        if shape and R ** 3 >= 216 and R ** 3 * 8 * p.J <= 60 * 1024:
+            expect[1] += 1
+    assert expect[0] > 0 and expect[1] > expect[0]
     h = ctypes.c_void_p()
     assert lib.mdp_build_batch(arr, len(insts), ctypes.byref(h)) == mdpvi.OK
     try:
-        assert lib.batch_vi_tile_instances(h) == expect
-        for mode in (-2, 2):
-            assert lib.batch_set_vi_tile(h, mode) == mdpvi.EINVAL, mode
-        assert lib.batch_set_vi_tile(h, 0) == mdpvi.OK
-        assert lib.batch_vi_tile_instances(h) == 0
-        assert lib.batch_set_vi_tile(h, 1) == mdpvi.OK
-        assert lib.batch_vi_tile_instances(h) == expect
+        assert lib.batch_tile_form_instances(h, 0) == expect[0]
+        assert lib.batch_tile_form_instances(h, 1) == 0
+        assert lib.batch_set_tile_form(h, 1, 1) == mdpvi.OK
+        assert lib.batch_tile_form_instances(h, 1) == expect[1]
+        for op, mode in ((0, -2), (1, 2), (2, 1), (-1, 0)):
+            assert lib.batch_set_tile_form(h, op, mode) == mdpvi.EINVAL, (op, mode)
+        assert lib.batch_tile_form_instances(h, 2) == -1
+        assert lib.batch_set_tile_form(h, 0, 0) == mdpvi.OK
+        assert lib.batch_tile_form_instances(h, 0) == 0
+        assert lib.batch_tile_form_instances(h, 1) == expect[1]
+        assert lib.batch_set_tile_form(h, 1, 0) == mdpvi.OK
+        assert lib.batch_tile_form_instances(h, 1) == 0
+        assert lib.batch_set_tile_form(h, 0, 1) == mdpvi.OK
+        assert lib.batch_tile_form_instances(h, 0) == expect[0]
     finally:
         lib.mdp_free_batch(h)
-    assert lib.batch_vi_tile_instances(None) == -1
+    assert lib.batch_tile_form_instances(None, 0) == -1

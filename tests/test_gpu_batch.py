@@ -140,14 +140,15 @@ def test_batch_round_forms_bit_identical_and_tuned(mdpvi, case):
         other.set_round_form("vi", 3)
 
 
-def test_batch_vi_tile_form_bit_identical(mdpvi):
-    """Value iteration's tile form (round-form instances of 4 or 5 hosts and
-    up to 3 distinct sizes, one (C+1)^3 tile per workgroup) gives the direct
-    round form's iterate bit for bit, with the same sweep counts: to
-    convergence from a sub-solution, and stopped after an odd number of
-    sweeps (the iterate then comes back from the second buffer).  The batch
-    mixes covered instances with ones the direct form keeps (a repeated task
-    size) and LDS-resident ones."""
+def test_batch_tile_forms_bit_identical(mdpvi):
+    """The tile forms of the round kernels (instances of 4 or 5 hosts and up
+    to 3 distinct sizes, one (C+1)^3 tile per workgroup) give the direct round
+    forms' results bit for bit, with the same sweep counts: value iteration to
+    convergence from a sub-solution and stopped after an odd number of sweeps
+    (the iterate then comes back from the second buffer), FP64 evaluation of
+    the extracted policy and of the least-loaded one, and policy iteration.
+    The batch mixes covered instances with ones the direct forms keep (a
+    repeated task size, small tiles) and LDS-resident ones."""
     import torch
     insts = list(W.batch(64, seed=3)) + [
         W.make(4, 12, (1, 1), (0.6, 0.4), 0.1, 0.02, (1.0, 1.3), 0.95),      # repeated sizes: direct
@@ -159,17 +160,29 @@ def test_batch_vi_tile_form_bit_identical(mdpvi):
         lb[b.offsets[i]:b.offsets[i + 1]] = sub_solution(p)
     outs = {}
     for mode in (0, 1):
-        b.set_vi_tile(mode)
-        n_tile = b.vi_tile_instances()
-        assert (n_tile > 0) == (mode == 1), (mode, n_tile)
+        b.set_tile_form("vi", mode)
+        b.set_tile_form("eval", mode)
+        n_vi, n_ev = b.tile_form_instances("vi"), b.tile_form_instances("eval")
+        assert (n_vi > 0) == (mode == 1) and (n_ev > 0) == (mode == 1), (mode, n_vi, n_ev)
         V = lb.clone()
         st, its, res = b.vi_solve(V, tol=1e-6)
         V7 = lb.clone()
         with pytest.raises(mdpvi.MdpviError) as e:
             b.vi_solve(V7, tol=1e-30, max_iter=7)
         assert e.value.code == mdpvi.ENOCONV
-        outs[mode] = (V.cpu().numpy().view(np.uint32), list(its), V7.cpu().numpy().view(np.uint32))
-        print(f"tile mode {mode}: {n_tile} instances in the tile form, {st['seconds'] * 1e3:.1f} ms", flush=True)
-    assert outs[0][1] == outs[1][1]
-    assert np.array_equal(outs[0][0], outs[1][0])
-    assert np.array_equal(outs[0][2], outs[1][2])
+        pi, _ = b.policy_extract(V, want_gap=False)
+        Vp, _, eits, _ = b.policy_eval(pi, V.double(), tol=1e-11)
+        pig = b.policy_greedy("least_loaded")
+        Vg, _, gits, _ = b.policy_eval(pig, torch.zeros_like(Vp), tol=1e-11)
+        Vpi = V.double()
+        _, rounds = b.policy_iteration(pi, Vpi, eval_tol=1e-11, improve_tol=1e-9)
+        outs[mode] = [V.cpu().numpy().view(np.uint32), list(its), V7.cpu().numpy().view(np.uint32),
+                      Vp.cpu().numpy().view(np.uint64), list(eits), Vg.cpu().numpy().view(np.uint64), list(gits),
+                      Vpi.cpu().numpy().view(np.uint64), pi.cpu().numpy(), list(rounds)]
+        print(f"tile mode {mode}: {n_vi} value-iteration and {n_ev} evaluation instances in the tile form, "
+              f"VI {st['seconds'] * 1e3:.1f} ms", flush=True)
+    for k, (x, y) in enumerate(zip(outs[0], outs[1])):
+        if isinstance(x, list):
+            assert x == y, k
+        else:
+            assert np.array_equal(x, y), k
