@@ -149,7 +149,8 @@ def supplementary_k7(mdpvi, tol: float) -> dict:
     impl = vi_kernel_name(vi_form)
     srcs = {"vi_row_kernel": ["paper_2012_12419_amd/csrc/row_vi.hip", "paper_2012_12419_amd/csrc/row.hpp",
                               "paper_2012_12419_amd/csrc/tile.hpp"],
-            "vi_tile_kernel": ["paper_2012_12419_amd/csrc/tile_vi.hip", "paper_2012_12419_amd/csrc/tile.hpp"]}
+            "vi_tile_kernel": ["paper_2012_12419_amd/csrc/tile_vi.hip", "paper_2012_12419_amd/csrc/tile_vi.hpp",
+                               "paper_2012_12419_amd/csrc/tile.hpp"]}
     return {"workload": f"large_single_k7: {desc}", "states": N, "form": vi_form, "kernel": impl,
             "sweeps": st["iterations"], "seconds": st["seconds"],
             "backups_per_s": st["backups"] / st["seconds"], "avg_us": avg * 1e6,
@@ -509,7 +510,8 @@ def main() -> int:
     if recs:
         vi_impl = vi_kernel_name(vi_form)
         ev_impl = "eval_tile_kernel" if ev_form >= mdpvi.FORM_TILE else "eval_exact_kernel"
-        srcs = {"vi_tile_kernel": ["paper_2012_12419_amd/csrc/tile_vi.hip", "paper_2012_12419_amd/csrc/tile.hpp"],
+        srcs = {"vi_tile_kernel": ["paper_2012_12419_amd/csrc/tile_vi.hip", "paper_2012_12419_amd/csrc/tile_vi.hpp",
+                                   "paper_2012_12419_amd/csrc/tile.hpp"],
                 "vi_row_kernel": ["paper_2012_12419_amd/csrc/row_vi.hip", "paper_2012_12419_amd/csrc/row.hpp",
                                   "paper_2012_12419_amd/csrc/tile.hpp"],
                 "vi_exact_kernel": ["paper_2012_12419_amd/csrc/sweep.hip",
@@ -517,6 +519,7 @@ def main() -> int:
                 "vi_slab_kernel": ["paper_2012_12419_amd/csrc/sweep.hip",
                                    "paper_2012_12419_amd/csrc/sweep_impl.hpp"],
                 "eval_tile_kernel": ["paper_2012_12419_amd/csrc/tile_eval.hip",
+                                     "paper_2012_12419_amd/csrc/tile_eval.hpp",
                                      "paper_2012_12419_amd/csrc/tile.hpp"],
                 "eval_exact_kernel": ["paper_2012_12419_amd/csrc/policy.hip",
                                       "paper_2012_12419_amd/csrc/policy_impl.hpp"]}
