@@ -380,9 +380,10 @@ int batch_round_forms(mdpvi_batch_t b, int32_t *opt);
  * of distinct sizes (a tuning knob: the same bits either way).  Each
  * workgroup stages one tile of (C+1)^3 occupancies in LDS (at most 60 KB;
  * value iteration: values and arrival terms of its round-form instances;
- * evaluation: values of the instances with tiles of at least 216
- * occupancies, the arrival terms of the actions then coming from FP64 side
- * arrays) and reads every neighbour along the three low digits from there;
+ * evaluation: values of the instances with tiles of at least 1,000
+ * occupancies whose values fit 32 KB, the arrival terms of the actions then
+ * coming from FP64 side arrays) and reads every neighbour along the three
+ * low digits from there;
  * the other instances keep the direct round kernels.  mode 1 on, 0 off, -1
  * automatic (the default: the choice batch_autotune recorded for the
  * batch's instance shapes, else on for value iteration and off for

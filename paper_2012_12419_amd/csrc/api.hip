@@ -1500,7 +1500,8 @@ int opt_index(int opt) { return opt == 1 ? 0 : opt == 2 ? 1 : 2; }
 // else the choice batch_autotune recorded for its shapes, else on for value
 // iteration and off for evaluation (on the 256-instance gradient batch the
 // tile form takes value iteration from 76 to 49 ms but evaluation to
-// tolerance from 121 to 148 ms).
+// tolerance from 122 to 141 ms: it covers some of the instances, and a round
+// then runs as two launches, each with its own tail).
 bool batch_tile_on(const mdpvi_batch* b, int op) {
   if ((op == 0 ? b->vt_tiles : b->et_tiles).empty()) return false;
   if (b->tile_mode[op] >= 0) return b->tile_mode[op] == 1;
@@ -1784,15 +1785,19 @@ int mdp_build_batch(const mdpvi_params* p, int32_t n, mdpvi_batch_t* out) {
     }
   }
   // FP64 evaluation's tile form: instances of 4 or 5 hosts and up to 3
-  // classes of distinct sizes whose (C+1)^3-occupancy tile has at least 216
-  // occupancies (one per lane of most of the workgroup) and fits the LDS
+  // classes of distinct sizes whose (C+1)^3-occupancy tile has at least
+  // 1,000 occupancies and whose FP64 values fit 32 KB of LDS (measured per
+  // round against the direct form on batches of 4- and 5-host instances:
+  // 16% faster at C+1 = 10..11; no faster at C+1 <= 9, whose tiles leave
+  // lanes idle, nor at C+1 = 12..13 with 3 classes, whose 41-52 KB of LDS
+  // allow three workgroups per CU)
   b->eocc.assign(n, 0);
   for (int i = 0; i < n; ++i) {
     const Model& M = b->models[i];
     const int64_t occ = static_cast<int64_t>(M.R) * M.R * M.R;
     const bool views = M.n_states < (int64_t{1} << 28);
-    if ((M.K == 4 || M.K == 5) && M.J <= 3 && M.n_sizes == M.J && views && occ >= 216 &&
-        occ * 8 * M.J <= static_cast<int64_t>(mdpvi::kBatchTileLds))
+    if ((M.K == 4 || M.K == 5) && M.J <= 3 && M.n_sizes == M.J && views && occ >= 1000 &&
+        occ * 8 * M.J <= static_cast<int64_t>(mdpvi::kBatchEvalTileLds))
       b->eocc[i] = static_cast<int32_t>(occ);
   }
   for (int i = 0; i < n; ++i) {

@@ -11,6 +11,7 @@ constexpr size_t kLdsBudget = 160 * 1024 - 1024;  // dynamic LDS per workgroup
 constexpr int kBatchExactK = 5;       // host counts up to which the round kernels
                                       // carry exact-shape backups
 constexpr size_t kBatchTileLds = 60 * 1024;   // dynamic LDS of a tile-form round workgroup
+constexpr size_t kBatchEvalTileLds = 32 * 1024;   // ... of the evaluation's tile form
 
 struct BatchInst {
   Model M;
