@@ -1499,9 +1499,8 @@ int opt_index(int opt) { return opt == 1 ? 0 : opt == 2 ? 1 : 2; }
 // the tile form for the instances it covers: the mode set on the batch,
 // else the choice batch_autotune recorded for its shapes, else on for value
 // iteration and off for evaluation (on the 256-instance gradient batch the
-// tile form takes value iteration from 76 to 49 ms but evaluation to
-// tolerance from 122 to 141 ms: it covers some of the instances, and a round
-// then runs as two launches, each with its own tail).
+// tile form takes value iteration from 76 to 49 ms, while evaluation to
+// tolerance stays at 123 ms with or without it).
 bool batch_tile_on(const mdpvi_batch* b, int op) {
   if ((op == 0 ? b->vt_tiles : b->et_tiles).empty()) return false;
   if (b->tile_mode[op] >= 0) return b->tile_mode[op] == 1;
@@ -2152,11 +2151,8 @@ int policy_eval_batch(mdpvi_batch_t b, const uint8_t* pi, double* V, double tol,
   return batch_all_rounds(
       b, L.t, L.n, L.t2, L.n2, tol, max_iter, s, st, iterations, residuals, 17.0,
       [&](long long j, const mdpvi::Tile* tiles, int n, const mdpvi::Tile* tiles2, int n2) {
-        const hipError_t e = mdpvi::launch_batch_eval_tile(b->d_inst, tiles2, n2, b->et_lds, pi, V, W, b->d_ctl,
-                                                           b->d_remaining, j, tol, b->d_E[0], b->d_E[1], s);
-        if (e != hipSuccess) return e;
-        return mdpvi::launch_batch_eval_round(b->d_inst, tiles, n, b->maxK, b->maxJ, pi, V, W, b->d_ctl,
-                                              b->d_remaining, j, tol, opt, s);
+        return mdpvi::launch_batch_eval_mixed(b->d_inst, tiles, n, tiles2, n2, b->et_lds, b->maxK, b->maxJ, pi, V, W,
+                                              b->d_ctl, b->d_remaining, j, tol, opt, b->d_E[0], b->d_E[1], s);
       },
       [&](int64_t issued) {
         return mdpvi::launch_batch_eval_finish(b->d_inst, b->d_all, b->n, V, W, b->d_ctl, issued, b->d_out, s);
@@ -2202,11 +2198,9 @@ int policy_iteration_batch(mdpvi_batch_t b, uint8_t* pi, double* V, double eval_
     rc = batch_all_rounds(
         b, L.t, L.n, L.t2, L.n2, eval_tol, eval_max_iter, s, &e, nullptr, nullptr, 17.0,
         [&](long long j, const mdpvi::Tile* tiles, int nt, const mdpvi::Tile* tiles2, int nt2) {
-          const hipError_t e = mdpvi::launch_batch_eval_tile(b->d_inst, tiles2, nt2, b->et_lds, pi, V, W, b->d_ctl,
-                                                             b->d_remaining, j, eval_tol, b->d_E[0], b->d_E[1], s);
-          if (e != hipSuccess) return e;
-          return mdpvi::launch_batch_eval_round(b->d_inst, tiles, nt, b->maxK, b->maxJ, pi, V, W, b->d_ctl,
-                                                b->d_remaining, j, eval_tol, opt, s);
+          return mdpvi::launch_batch_eval_mixed(b->d_inst, tiles, nt, tiles2, nt2, b->et_lds, b->maxK, b->maxJ, pi, V,
+                                                W, b->d_ctl, b->d_remaining, j, eval_tol, opt, b->d_E[0], b->d_E[1],
+                                                s);
         },
         [&](int64_t issued) {
           return mdpvi::launch_batch_eval_finish(b->d_inst, b->d_all, n, V, W, b->d_ctl, issued, b->d_out, s);
@@ -2414,10 +2408,9 @@ int batch_autotune(mdpvi_batch_t b, int32_t trials, void* hip_stream, int32_t* o
         for (int r = -1; r < trials; ++r) {
           HIP_TRY(mdpvi::launch_batch_ctl_init(b->d_ctl, b->d_all, b->n, b->d_remaining, b->d_flags, 0, s));
           HIP_TRY(hipEventRecord(b->ev0, s));
-          HIP_TRY(mdpvi::launch_batch_eval_tile(b->d_inst, b->d_et_tiles, net, b->et_lds, pol, v64, w64, b->d_ctl,
-                                                b->d_remaining, 0, 1.0, b->d_E[0], b->d_E[1], s));
-          HIP_TRY(mdpvi::launch_batch_eval_round(b->d_inst, b->d_rtiles_all_nt[oi], nt, b->maxK, b->maxJ, pol, v64,
-                                                 w64, b->d_ctl, b->d_remaining, 0, 1.0, best, s));
+          HIP_TRY(mdpvi::launch_batch_eval_mixed(b->d_inst, b->d_rtiles_all_nt[oi], nt, b->d_et_tiles, net, b->et_lds,
+                                                 b->maxK, b->maxJ, pol, v64, w64, b->d_ctl, b->d_remaining, 0, 1.0,
+                                                 best, b->d_E[0], b->d_E[1], s));
           HIP_TRY(hipEventRecord(b->ev1, s));
           HIP_TRY(hipEventSynchronize(b->ev1));
           if (r >= 0) HIP_TRY(hipEventElapsedTime(&ms[r], b->ev0, b->ev1));

@@ -346,16 +346,12 @@ __device__ __forceinline__ double round_tile_exact(const Model& M, const uint8_t
 // instance when EXACT is false, the generic one.  A tile holds kBlock * opt
 // occupancies, opt per thread (opt in 1..kOccPerThread).
 template <class Op, int KMAX, int JMAX, bool EXACT>
-__global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __restrict__ insts,
-                                                              const Tile* __restrict__ tiles,
-                                                              typename Op::T* __restrict__ V,
-                                                              typename Op::T* __restrict__ W,
-                                                              const uint8_t* __restrict__ pi,
-                                                              BatchCtl* __restrict__ ctl,
-                                                              int* remaining, long long j, double tol,
-                                                              int opt, double* A0, double* A1) {
+__device__ __forceinline__ void round_body(const BatchInst* __restrict__ insts, const Tile tile,
+                                           typename Op::T* __restrict__ V, typename Op::T* __restrict__ W,
+                                           const uint8_t* __restrict__ pi, BatchCtl* __restrict__ ctl,
+                                           int* remaining, long long j, double tol, int opt, double* A0,
+                                           double* A1) {
   using T = typename Op::T;
-  const Tile tile = tiles[blockIdx.x];
   const BatchInst& I = insts[tile.inst];
   const Model& M = I.M;
   BatchCtl* c = ctl + tile.inst;
@@ -395,6 +391,18 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
     }
   }
   round_residual<Op::RK>(acc, c, j, (tile.first / kBlock) % kBatchLanes);
+}
+
+template <class Op, int KMAX, int JMAX, bool EXACT>
+__global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __restrict__ insts,
+                                                              const Tile* __restrict__ tiles,
+                                                              typename Op::T* __restrict__ V,
+                                                              typename Op::T* __restrict__ W,
+                                                              const uint8_t* __restrict__ pi,
+                                                              BatchCtl* __restrict__ ctl,
+                                                              int* remaining, long long j, double tol,
+                                                              int opt, double* A0, double* A1) {
+  round_body<Op, KMAX, JMAX, EXACT>(insts, tiles[blockIdx.x], V, W, pi, ctl, remaining, j, tol, opt, A0, A1);
 }
 
 // Value-iteration round in the tile form (tile_vi.hpp) for the instances
@@ -476,14 +484,11 @@ __global__ __launch_bounds__(kBlock) void batch_vi_tile_kernel(const BatchInst* 
 // arrays (E0/E1 + eoff, ping-pong with the values), written by the previous
 // round or by batch_eval_arrival_init_kernel: the same bits as the direct
 // round backup.
-__global__ __launch_bounds__(kBlock) void batch_eval_tile_kernel(const BatchInst* __restrict__ insts,
-                                                                  const Tile* __restrict__ tiles,
-                                                                  const uint8_t* __restrict__ pi,
-                                                                  double* __restrict__ V, double* __restrict__ W,
-                                                                  BatchCtl* __restrict__ ctl, int* remaining,
-                                                                  long long j, double tol, double* E0, double* E1) {
-  extern __shared__ double tile_lds[];
-  const Tile tile = tiles[blockIdx.x];
+__device__ __forceinline__ void eval_tile_round(const BatchInst* __restrict__ insts, const Tile tile,
+                                                const uint8_t* __restrict__ pi, double* __restrict__ V,
+                                                double* __restrict__ W, BatchCtl* __restrict__ ctl, int* remaining,
+                                                long long j, double tol, double* E0, double* E1,
+                                                double* tile_lds) {
   const BatchInst& I = insts[tile.inst];
   const Model& M = I.M;
   BatchCtl* c = ctl + tile.inst;
@@ -506,6 +511,36 @@ __global__ __launch_bounds__(kBlock) void batch_eval_tile_kernel(const BatchInst
     default: acc = NAN;   // not a tile-form shape: the host never lists such a tile
   }
   round_residual<ResKind::kMax>(acc, c, j, tile.first % kBatchLanes);
+}
+
+__global__ __launch_bounds__(kBlock) void batch_eval_tile_kernel(const BatchInst* __restrict__ insts,
+                                                                  const Tile* __restrict__ tiles,
+                                                                  const uint8_t* __restrict__ pi,
+                                                                  double* __restrict__ V, double* __restrict__ W,
+                                                                  BatchCtl* __restrict__ ctl, int* remaining,
+                                                                  long long j, double tol, double* E0, double* E1) {
+  extern __shared__ double tile_lds[];
+  eval_tile_round(insts, tiles[blockIdx.x], pi, V, W, ctl, remaining, j, tol, E0, E1, tile_lds);
+}
+
+// One evaluation round over both kinds of tile in one launch (one tail per
+// round): workgroups 0..n_tile-1 take the tile-form tiles, the rest the
+// direct-form ones (the exact-shape round backup; every instance of the
+// batch has at most kBatchExactK hosts and 3 classes).
+__global__ __launch_bounds__(kBlock) void batch_eval_mixed_kernel(const BatchInst* __restrict__ insts,
+                                                                   const Tile* __restrict__ dtiles,
+                                                                   const Tile* __restrict__ ttiles, int n_tile,
+                                                                   const uint8_t* __restrict__ pi,
+                                                                   double* __restrict__ V, double* __restrict__ W,
+                                                                   BatchCtl* __restrict__ ctl, int* remaining,
+                                                                   long long j, double tol, int opt, double* E0,
+                                                                   double* E1) {
+  extern __shared__ double tile_lds[];
+  if (static_cast<int>(blockIdx.x) < n_tile)
+    eval_tile_round(insts, ttiles[blockIdx.x], pi, V, W, ctl, remaining, j, tol, E0, E1, tile_lds);
+  else
+    round_body<EvalOp, 8, 4, true>(insts, dtiles[blockIdx.x - n_tile], V, W, pi, ctl, remaining, j, tol, opt,
+                                   nullptr, nullptr);
 }
 
 // A(o) = sum_e lambda_e/Lam V(o, e) (the FMA chain of the evaluation
@@ -915,6 +950,25 @@ hipError_t launch_batch_eval_tile(const BatchInst* insts, const Tile* tiles, int
   if (E0 == nullptr || E1 == nullptr || lds == 0 || lds > kBatchTileLds) return hipErrorInvalidValue;
   hipLaunchKernelGGL(batch_eval_tile_kernel, dim3(n_tiles), dim3(kBlock), lds, s, insts, tiles, pi, V, W, ctl,
                      remaining, j, tol, E0, E1);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_eval_mixed(const BatchInst* insts, const Tile* dtiles, int n_direct, const Tile* ttiles,
+                                   int n_tile, size_t lds, int maxK, int maxJ, const uint8_t* pi, double* V,
+                                   double* W, BatchCtl* ctl, int* remaining, long long j, double tol, int opt,
+                                   double* E0, double* E1, hipStream_t s) {
+  if (n_tile == 0)
+    return launch_batch_eval_round(insts, dtiles, n_direct, maxK, maxJ, pi, V, W, ctl, remaining, j, tol, opt, s);
+  if (n_direct == 0 || !(maxK <= kBatchExactK && maxJ <= 3)) {
+    const hipError_t e = launch_batch_eval_tile(insts, ttiles, n_tile, lds, pi, V, W, ctl, remaining, j, tol, E0,
+                                                E1, s);
+    if (e != hipSuccess) return e;
+    return launch_batch_eval_round(insts, dtiles, n_direct, maxK, maxJ, pi, V, W, ctl, remaining, j, tol, opt, s);
+  }
+  if (opt < 1 || opt > kOccPerThread || E0 == nullptr || E1 == nullptr || lds == 0 || lds > kBatchTileLds)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(batch_eval_mixed_kernel, dim3(n_tile + n_direct), dim3(kBlock), lds, s, insts, dtiles, ttiles,
+                     n_tile, pi, V, W, ctl, remaining, j, tol, opt, E0, E1);
   return hipGetLastError();
 }
 

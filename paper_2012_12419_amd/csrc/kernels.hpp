@@ -161,6 +161,13 @@ hipError_t launch_batch_eval_tile(const BatchInst* insts, const Tile* tiles, int
                                   long long j, double tol, double* E0, double* E1, hipStream_t s);
 hipError_t launch_batch_eval_arrival_init(const BatchInst* insts, const Tile* tiles, int n_tiles, const double* V,
                                           double* E0, hipStream_t s);
+// One evaluation round over direct-form tiles and tile-form tiles: a single
+// launch carrying both kinds of workgroup when the batch's instances all
+// have at most kBatchExactK hosts and 3 classes, else the two launches.
+hipError_t launch_batch_eval_mixed(const BatchInst* insts, const Tile* dtiles, int n_direct, const Tile* ttiles,
+                                   int n_tile, size_t lds, int maxK, int maxJ, const uint8_t* pi, double* V,
+                                   double* W, BatchCtl* ctl, int* remaining, long long j, double tol, int opt,
+                                   double* E0, double* E1, hipStream_t s);
 // The arrival terms of V (the initial iterate) into A0, the -inf entries
 // into A0 and A1, for the instances of the tiles that have side arrays.
 hipError_t launch_batch_arrival_init(const BatchInst* insts, const Tile* tiles, int n_tiles, const float* V,
