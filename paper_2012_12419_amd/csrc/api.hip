@@ -681,6 +681,8 @@ struct mdpvi_batch {
   int64_t e_total = 0;                   // their length: sum of n_occ
   int tile_mode[2] = {-1, -1};           // tile form of value iteration and evaluation:
                                          // -1 automatic, 0 off, 1 on
+  bool exact_all[3] = {false, false, false};   // per operation: every instance it rounds over meets
+                                               // the exact-shape round backup's terms
   int round_opt[3] = {0, 0, 0};          // per operation (value iteration, evaluation, adjoint):
                                          // occupancies per thread, 0 automatic
   int lds_maxK = 1, lds_maxJ = 1, rnd_maxK = 1, rnd_maxJ = 1, maxK = 1, maxJ = 1;
@@ -1812,6 +1814,18 @@ int mdp_build_batch(const mdpvi_params* p, int32_t n, mdpvi_batch_t* out) {
       }
     }
   }
+  // the exact-shape round backups' terms (the device-side exact_ok of each
+  // operation): value iteration over the round-form instances, evaluation
+  // and the adjoint over all
+  b->exact_all[0] = b->exact_all[1] = b->exact_all[2] = true;
+  for (int i = 0; i < n; ++i) {
+    const Model& M = b->models[i];
+    const bool shape = M.K <= mdpvi::kBatchExactK && M.J <= 3;
+    if (M.n_states > lds_states && !(shape && M.n_sizes == M.J && M.n_states < (int64_t{1} << 29)))
+      b->exact_all[0] = false;
+    if (!(shape && M.n_states < (int64_t{1} << 28))) b->exact_all[1] = false;
+    if (!shape) b->exact_all[2] = false;
+  }
   std::sort(cost.begin(), cost.end(), [](auto& x, auto& y) { return x.first > y.first; });
   for (auto& c : cost) b->lds_list.push_back(c.second);
   b->lds_bytes = static_cast<size_t>(2 * max_lds_n) * sizeof(float);
@@ -1927,7 +1941,8 @@ int vi_solve_batch(mdpvi_batch_t b, float* V, double tol, int64_t max_iter, void
         HIP_TRY(mdpvi::launch_batch_vi_tile(b->d_inst, vtiles, nvt, b->vt_lds, V, b->W, b->d_ctl, b->d_remaining,
                                             issued + k, tol, b->d_A[0], b->d_A[1], s));
         HIP_TRY(mdpvi::launch_batch_round(b->d_inst, tiles, nt, b->rnd_maxK, b->rnd_maxJ, V, b->W, b->d_ctl,
-                                          b->d_remaining, issued + k, tol, opt, b->d_A[0], b->d_A[1], s));
+                                          b->d_remaining, issued + k, tol, opt, b->d_A[0], b->d_A[1],
+                                          b->exact_all[0], s));
       }
       issued += m;
       // drop the tiles of instances that have stopped from the next chunk
@@ -2152,7 +2167,8 @@ int policy_eval_batch(mdpvi_batch_t b, const uint8_t* pi, double* V, double tol,
       b, L.t, L.n, L.t2, L.n2, tol, max_iter, s, st, iterations, residuals, 17.0,
       [&](long long j, const mdpvi::Tile* tiles, int n, const mdpvi::Tile* tiles2, int n2) {
         return mdpvi::launch_batch_eval_mixed(b->d_inst, tiles, n, tiles2, n2, b->et_lds, b->maxK, b->maxJ, pi, V, W,
-                                              b->d_ctl, b->d_remaining, j, tol, opt, b->d_E[0], b->d_E[1], s);
+                                              b->d_ctl, b->d_remaining, j, tol, opt, b->d_E[0], b->d_E[1],
+                                              b->exact_all[1], s);
       },
       [&](int64_t issued) {
         return mdpvi::launch_batch_eval_finish(b->d_inst, b->d_all, b->n, V, W, b->d_ctl, issued, b->d_out, s);
@@ -2200,7 +2216,7 @@ int policy_iteration_batch(mdpvi_batch_t b, uint8_t* pi, double* V, double eval_
         [&](long long j, const mdpvi::Tile* tiles, int nt, const mdpvi::Tile* tiles2, int nt2) {
           return mdpvi::launch_batch_eval_mixed(b->d_inst, tiles, nt, tiles2, nt2, b->et_lds, b->maxK, b->maxJ, pi, V,
                                                 W, b->d_ctl, b->d_remaining, j, eval_tol, opt, b->d_E[0], b->d_E[1],
-                                                s);
+                                                b->exact_all[1], s);
         },
         [&](int64_t issued) {
           return mdpvi::launch_batch_eval_finish(b->d_inst, b->d_all, n, V, W, b->d_ctl, issued, b->d_out, s);
@@ -2252,7 +2268,8 @@ int vi_adjoint_batch(mdpvi_batch_t b, const uint8_t* pi, const double* V_pi, flo
       max_iter, s, st, iterations, nullptr, 9.0,
       [&](long long j, const mdpvi::Tile* tiles, int n, const mdpvi::Tile*, int) {
         return mdpvi::launch_batch_adjoint_round(b->d_inst, tiles, n, b->maxK, b->maxJ, pi, w, b->W,
-                                                 b->d_ctl, b->d_remaining, j, tol, opt, b->d_lines, s);
+                                                 b->d_ctl, b->d_remaining, j, tol, opt, b->d_lines,
+                                                 b->exact_all[2], s);
       },
       [&](int64_t issued) {
         return mdpvi::launch_batch_adjoint_finish(b->d_inst, b->d_all, b->n, w, b->W, b->d_ctl, issued, b->d_out,
@@ -2347,12 +2364,13 @@ int batch_autotune(mdpvi_batch_t b, int32_t trials, void* hip_stream, int32_t* o
         auto round = [&]() -> hipError_t {
           if (op == 0)
             return mdpvi::launch_batch_round(b->d_inst, tiles, nt, b->rnd_maxK, b->rnd_maxJ, v32, b->W, b->d_ctl,
-                                             b->d_remaining, 0, 1.0, o, b->d_A[0], b->d_A[1], s);
+                                             b->d_remaining, 0, 1.0, o, b->d_A[0], b->d_A[1], b->exact_all[0], s);
           if (op == 1)
             return mdpvi::launch_batch_eval_round(b->d_inst, tiles, nt, b->maxK, b->maxJ, pol, v64, w64, b->d_ctl,
-                                                  b->d_remaining, 0, 1.0, o, s);
+                                                  b->d_remaining, 0, 1.0, o, b->exact_all[1], s);
           return mdpvi::launch_batch_adjoint_round(b->d_inst, tiles, nt, b->maxK, b->maxJ, pol, v32, b->W,
-                                                   b->d_ctl, b->d_remaining, 0, 1.0, o, b->d_lines, s);
+                                                   b->d_ctl, b->d_remaining, 0, 1.0, o, b->d_lines,
+                                                   b->exact_all[2], s);
         };
         std::vector<float> ms(trials);
         for (int r = -1; r < trials; ++r) {   // r = -1: untimed first launch
@@ -2388,7 +2406,8 @@ int batch_autotune(mdpvi_batch_t b, int32_t trials, void* hip_stream, int32_t* o
           HIP_TRY(mdpvi::launch_batch_vi_tile(b->d_inst, b->d_vt_tiles, nvt, b->vt_lds, v32, b->W, b->d_ctl,
                                               b->d_remaining, 0, 1.0, b->d_A[0], b->d_A[1], s));
           HIP_TRY(mdpvi::launch_batch_round(b->d_inst, b->d_rtiles_nt[oi], nt, b->rnd_maxK, b->rnd_maxJ, v32, b->W,
-                                            b->d_ctl, b->d_remaining, 0, 1.0, best, b->d_A[0], b->d_A[1], s));
+                                            b->d_ctl, b->d_remaining, 0, 1.0, best, b->d_A[0], b->d_A[1],
+                                            b->exact_all[0], s));
           HIP_TRY(hipEventRecord(b->ev1, s));
           HIP_TRY(hipEventSynchronize(b->ev1));
           if (r >= 0) HIP_TRY(hipEventElapsedTime(&ms[r], b->ev0, b->ev1));
@@ -2410,7 +2429,7 @@ int batch_autotune(mdpvi_batch_t b, int32_t trials, void* hip_stream, int32_t* o
           HIP_TRY(hipEventRecord(b->ev0, s));
           HIP_TRY(mdpvi::launch_batch_eval_mixed(b->d_inst, b->d_rtiles_all_nt[oi], nt, b->d_et_tiles, net, b->et_lds,
                                                  b->maxK, b->maxJ, pol, v64, w64, b->d_ctl, b->d_remaining, 0, 1.0,
-                                                 best, b->d_E[0], b->d_E[1], s));
+                                                 best, b->d_E[0], b->d_E[1], b->exact_all[1], s));
           HIP_TRY(hipEventRecord(b->ev1, s));
           HIP_TRY(hipEventSynchronize(b->ev1));
           if (r >= 0) HIP_TRY(hipEventElapsedTime(&ms[r], b->ev0, b->ev1));

@@ -340,12 +340,18 @@ __device__ __forceinline__ double round_tile_exact(const Model& M, const uint8_t
   return acc;
 }
 
-// EXACT: instances of up to kBatchExactK hosts and 3 classes that meet
-// Op::exact_ok take the exact-shape backup of their own (K, J) (a uniform
-// branch per workgroup: a tile belongs to one instance); others, and every
-// instance when EXACT is false, the generic one.  A tile holds kBlock * opt
-// occupancies, opt per thread (opt in 1..kOccPerThread).
-template <class Op, int KMAX, int JMAX, bool EXACT>
+// FORM kRoundExact: instances of up to kBatchExactK hosts and 3 classes
+// that meet Op::exact_ok take the exact-shape backup of their own (K, J) (a
+// uniform branch per workgroup: a tile belongs to one instance), others the
+// generic one; kRoundGeneric: every instance the generic one;
+// kRoundExactOnly: the exact-shape backups alone (the host launches it when
+// every instance qualifies; without the generic body the kernel needs far
+// fewer registers), an instance that does not qualify reporting a NaN
+// residual.  A tile holds kBlock * opt occupancies, opt per thread (opt in
+// 1..kOccPerThread).
+constexpr int kRoundGeneric = 0, kRoundExact = 1, kRoundExactOnly = 2;
+
+template <class Op, int KMAX, int JMAX, int FORM>
 __device__ __forceinline__ void round_body(const BatchInst* __restrict__ insts, const Tile tile,
                                            typename Op::T* __restrict__ V, typename Op::T* __restrict__ W,
                                            const uint8_t* __restrict__ pi, BatchCtl* __restrict__ ctl,
@@ -361,7 +367,7 @@ __device__ __forceinline__ void round_body(const BatchInst* __restrict__ insts, 
   const uint8_t* p = pi ? pi + I.offset : nullptr;
   double acc = 0.0;
   bool done = false;
-  if constexpr (EXACT) {
+  if constexpr (FORM != kRoundGeneric) {
     const double* Ain = nullptr;
     double* Aout = nullptr;
     if (Op::exact_ok(I) && Op::side(I, j, A0, A1, &Ain, &Aout)) {
@@ -380,20 +386,24 @@ __device__ __forceinline__ void round_body(const BatchInst* __restrict__ insts, 
       static_assert(kBatchExactK == 5, "the cases above cover K = 1..kBatchExactK");
     }
   }
-  if (!done) {
-    for (int k = 0; k < opt; ++k) {
-      const uint32_t o = tile.first + threadIdx.x + k * kBlock;
-      if (o < static_cast<uint32_t>(M.n_occ)) {
-        const double d = Op::template run<KMAX, JMAX>(M, p, Vin, Vout, o);
-        if constexpr (Op::RK == ResKind::kMax) acc = (d > acc || d != d) ? d : acc;
-        else acc += d;
+  if constexpr (FORM == kRoundExactOnly) {
+    if (!done) acc = NAN;
+  } else {
+    if (!done) {
+      for (int k = 0; k < opt; ++k) {
+        const uint32_t o = tile.first + threadIdx.x + k * kBlock;
+        if (o < static_cast<uint32_t>(M.n_occ)) {
+          const double d = Op::template run<KMAX, JMAX>(M, p, Vin, Vout, o);
+          if constexpr (Op::RK == ResKind::kMax) acc = (d > acc || d != d) ? d : acc;
+          else acc += d;
+        }
       }
     }
   }
   round_residual<Op::RK>(acc, c, j, (tile.first / kBlock) % kBatchLanes);
 }
 
-template <class Op, int KMAX, int JMAX, bool EXACT>
+template <class Op, int KMAX, int JMAX, int FORM>
 __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __restrict__ insts,
                                                               const Tile* __restrict__ tiles,
                                                               typename Op::T* __restrict__ V,
@@ -402,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
                                                               BatchCtl* __restrict__ ctl,
                                                               int* remaining, long long j, double tol,
                                                               int opt, double* A0, double* A1) {
-  round_body<Op, KMAX, JMAX, EXACT>(insts, tiles[blockIdx.x], V, W, pi, ctl, remaining, j, tol, opt, A0, A1);
+  round_body<Op, KMAX, JMAX, FORM>(insts, tiles[blockIdx.x], V, W, pi, ctl, remaining, j, tol, opt, A0, A1);
 }
 
 // Value-iteration round in the tile form (tile_vi.hpp) for the instances
@@ -539,8 +549,8 @@ __global__ __launch_bounds__(kBlock) void batch_eval_mixed_kernel(const BatchIns
   if (static_cast<int>(blockIdx.x) < n_tile)
     eval_tile_round(insts, ttiles[blockIdx.x], pi, V, W, ctl, remaining, j, tol, E0, E1, tile_lds);
   else
-    round_body<EvalOp, 8, 4, true>(insts, dtiles[blockIdx.x - n_tile], V, W, pi, ctl, remaining, j, tol, opt,
-                                   nullptr, nullptr);
+    round_body<EvalOp, 8, 4, kRoundExact>(insts, dtiles[blockIdx.x - n_tile], V, W, pi, ctl, remaining, j, tol,
+                                          opt, nullptr, nullptr);
 }
 
 // A(o) = sum_e lambda_e/Lam V(o, e) (the FMA chain of the evaluation
@@ -910,17 +920,21 @@ template <class Op>
 static hipError_t launch_round_t(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                  int maxJ, typename Op::T* V, typename Op::T* W, const uint8_t* pi,
                                  BatchCtl* ctl, int* remaining, long long j, double tol, int opt,
-                                 double* A0, double* A1, hipStream_t s) {
+                                 double* A0, double* A1, bool all_exact, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   if (opt < 1 || opt > kOccPerThread) return hipErrorInvalidValue;
   if (maxK <= kBatchExactK && maxJ <= 3) {
-    hipLaunchKernelGGL((batch_round_kernel<Op, 8, 4, true>), dim3(n_tiles), dim3(kBlock), 0, s, insts, tiles,
-                       V, W, pi, ctl, remaining, j, tol, opt, A0, A1);
+    if (all_exact)
+      hipLaunchKernelGGL((batch_round_kernel<Op, 8, 4, kRoundExactOnly>), dim3(n_tiles), dim3(kBlock), 0, s, insts,
+                         tiles, V, W, pi, ctl, remaining, j, tol, opt, A0, A1);
+    else
+      hipLaunchKernelGGL((batch_round_kernel<Op, 8, 4, kRoundExact>), dim3(n_tiles), dim3(kBlock), 0, s, insts,
+                         tiles, V, W, pi, ctl, remaining, j, tol, opt, A0, A1);
     return hipGetLastError();
   }
   return dispatch_kj_b(maxK, maxJ, [&](auto km, auto jm) {
     constexpr int KM = decltype(km)::value, JM = decltype(jm)::value;
-    hipLaunchKernelGGL((batch_round_kernel<Op, KM, JM, false>), dim3(n_tiles), dim3(kBlock), 0, s, insts,
+    hipLaunchKernelGGL((batch_round_kernel<Op, KM, JM, kRoundGeneric>), dim3(n_tiles), dim3(kBlock), 0, s, insts,
                        tiles, V, W, pi, ctl, remaining, j, tol, opt, A0, A1);
     return hipGetLastError();
   });
@@ -928,9 +942,10 @@ static hipError_t launch_round_t(const BatchInst* insts, const Tile* tiles, int 
 
 hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                               int maxJ, float* V, float* W, BatchCtl* ctl, int* remaining,
-                              long long j, double tol, int opt, double* A0, double* A1, hipStream_t s) {
+                              long long j, double tol, int opt, double* A0, double* A1, bool all_exact,
+                              hipStream_t s) {
   return launch_round_t<VIOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, nullptr, ctl, remaining, j, tol, opt,
-                              A0, A1, s);
+                              A0, A1, all_exact && A0 != nullptr, s);
 }
 
 hipError_t launch_batch_vi_tile(const BatchInst* insts, const Tile* tiles, int n_tiles, size_t lds, float* V,
@@ -956,14 +971,16 @@ hipError_t launch_batch_eval_tile(const BatchInst* insts, const Tile* tiles, int
 hipError_t launch_batch_eval_mixed(const BatchInst* insts, const Tile* dtiles, int n_direct, const Tile* ttiles,
                                    int n_tile, size_t lds, int maxK, int maxJ, const uint8_t* pi, double* V,
                                    double* W, BatchCtl* ctl, int* remaining, long long j, double tol, int opt,
-                                   double* E0, double* E1, hipStream_t s) {
+                                   double* E0, double* E1, bool all_exact, hipStream_t s) {
   if (n_tile == 0)
-    return launch_batch_eval_round(insts, dtiles, n_direct, maxK, maxJ, pi, V, W, ctl, remaining, j, tol, opt, s);
+    return launch_batch_eval_round(insts, dtiles, n_direct, maxK, maxJ, pi, V, W, ctl, remaining, j, tol, opt,
+                                   all_exact, s);
   if (n_direct == 0 || !(maxK <= kBatchExactK && maxJ <= 3)) {
     const hipError_t e = launch_batch_eval_tile(insts, ttiles, n_tile, lds, pi, V, W, ctl, remaining, j, tol, E0,
                                                 E1, s);
     if (e != hipSuccess) return e;
-    return launch_batch_eval_round(insts, dtiles, n_direct, maxK, maxJ, pi, V, W, ctl, remaining, j, tol, opt, s);
+    return launch_batch_eval_round(insts, dtiles, n_direct, maxK, maxJ, pi, V, W, ctl, remaining, j, tol, opt,
+                                   all_exact, s);
   }
   if (opt < 1 || opt > kOccPerThread || E0 == nullptr || E1 == nullptr || lds == 0 || lds > kBatchTileLds)
     return hipErrorInvalidValue;
@@ -981,15 +998,16 @@ hipError_t launch_batch_eval_arrival_init(const BatchInst* insts, const Tile* ti
 
 hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                    int maxJ, const uint8_t* pi, double* V, double* W, BatchCtl* ctl,
-                                   int* remaining, long long j, double tol, int opt, hipStream_t s) {
+                                   int* remaining, long long j, double tol, int opt, bool all_exact,
+                                   hipStream_t s) {
   return launch_round_t<EvalOp>(insts, tiles, n_tiles, maxK, maxJ, V, W, pi, ctl, remaining, j, tol, opt,
-                                nullptr, nullptr, s);
+                                nullptr, nullptr, all_exact, s);
 }
 
 hipError_t launch_batch_adjoint_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                       int maxJ, const uint8_t* pi, float* w, float* W, BatchCtl* ctl,
                                       int* remaining, long long j, double tol, int opt, double* lines,
-                                      hipStream_t s) {
+                                      bool all_exact, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   if (opt < 1 || opt > kOccPerThread) return hipErrorInvalidValue;
   // the table is read only by the exact backups of the kernel below
@@ -1001,7 +1019,7 @@ hipError_t launch_batch_adjoint_round(const BatchInst* insts, const Tile* tiles,
     if (e != hipSuccess) return e;
   }
   return launch_round_t<AdjOp>(insts, tiles, n_tiles, maxK, maxJ, w, W, pi, ctl, remaining, j, tol, opt, lines,
-                               nullptr, s);
+                               nullptr, all_exact && lines != nullptr, s);
 }
 
 template <typename T, ResKind RK>

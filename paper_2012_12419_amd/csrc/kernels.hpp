@@ -140,10 +140,15 @@ hipError_t launch_batch_ctl_init(BatchCtl* ctl, const int32_t* list, int n_list,
 // given tiles (kBlock * opt occupancies each, opt in 1..kOccPerThread).
 // Value iteration's round reads and writes the FP64 arrival terms of the
 // instances with side arrays in A0/A1 (ping-pong like V/W; nullptr: every
-// instance takes the backup without them).
+// instance takes the backup without them).  all_exact (every round
+// launcher): every instance of the tiles meets the exact-shape backup's
+// terms (at most kBatchExactK hosts, 3 classes; value iteration: distinct
+// sizes and side arrays; the adjoint: a line table), which selects a kernel
+// without the generic backup (fewer registers).
 hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                               int maxJ, float* V, float* W, BatchCtl* ctl, int* remaining,
-                              long long j, double tol, int opt, double* A0, double* A1, hipStream_t s);
+                              long long j, double tol, int opt, double* A0, double* A1, bool all_exact,
+                              hipStream_t s);
 // Value iteration's round in the tile form over tiles {inst, tile index} of
 // instances with tocc > 0 (K in 4..5, J <= 3 distinct sizes); lds: bytes of
 // dynamic LDS, at least (tocc + 1) * 8 + J * tocc * 4 for every listed
@@ -167,14 +172,15 @@ hipError_t launch_batch_eval_arrival_init(const BatchInst* insts, const Tile* ti
 hipError_t launch_batch_eval_mixed(const BatchInst* insts, const Tile* dtiles, int n_direct, const Tile* ttiles,
                                    int n_tile, size_t lds, int maxK, int maxJ, const uint8_t* pi, double* V,
                                    double* W, BatchCtl* ctl, int* remaining, long long j, double tol, int opt,
-                                   double* E0, double* E1, hipStream_t s);
+                                   double* E0, double* E1, bool all_exact, hipStream_t s);
 // The arrival terms of V (the initial iterate) into A0, the -inf entries
 // into A0 and A1, for the instances of the tiles that have side arrays.
 hipError_t launch_batch_arrival_init(const BatchInst* insts, const Tile* tiles, int n_tiles, const float* V,
                                      double* A0, double* A1, int opt, hipStream_t s);
 hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                    int maxJ, const uint8_t* pi, double* V, double* W, BatchCtl* ctl,
-                                   int* remaining, long long j, double tol, int opt, hipStream_t s);
+                                   int* remaining, long long j, double tol, int opt, bool all_exact,
+                                   hipStream_t s);
 // The adjoint's round: with a line table (lines != nullptr; the instances'
 // loff entries) the reset-line sums of the round's input are written to it
 // first and the exact backups read them; nullptr: every instance sums its
@@ -182,7 +188,7 @@ hipError_t launch_batch_eval_round(const BatchInst* insts, const Tile* tiles, in
 hipError_t launch_batch_adjoint_round(const BatchInst* insts, const Tile* tiles, int n_tiles, int maxK,
                                       int maxJ, const uint8_t* pi, float* w, float* W, BatchCtl* ctl,
                                       int* remaining, long long j, double tol, int opt, double* lines,
-                                      hipStream_t s);
+                                      bool all_exact, hipStream_t s);
 hipError_t launch_batch_round_finish(const BatchInst* insts, const int32_t* list, int n_list,
                                      float* V, const float* W, BatchCtl* ctl, long long issued,
                                      BatchOut* out, hipStream_t s);
