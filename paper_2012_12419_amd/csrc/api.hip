@@ -1776,8 +1776,7 @@ int mdp_build_batch(const mdpvi_params* p, int32_t n, mdpvi_batch_t* out) {
     if (b->tocc[i] > 0) {
       const uint32_t nt = static_cast<uint32_t>(M.n_occ / b->tocc[i]);
       for (uint32_t t = 0; t < nt; ++t) b->vt_tiles.push_back({i, t});
-      b->vt_lds = std::max(b->vt_lds, static_cast<size_t>(b->tocc[i] + 1) * 8 +
-                                          static_cast<size_t>(b->tocc[i]) * 4 * M.J);
+      b->vt_lds = std::max(b->vt_lds, static_cast<size_t>(b->tocc[i]) * 4 * M.J);
     } else {
       for (int oi = 0; oi < 3; ++oi) {
         const uint32_t per = static_cast<uint32_t>(mdpvi::kBlock) << oi;

@@ -418,12 +418,13 @@ __global__ __launch_bounds__(kBlock) void batch_round_kernel(const BatchInst* __
 // Value-iteration round in the tile form (tile_vi.hpp) for the instances
 // with I.tocc > 0 (K in 4..5, J <= 3 distinct sizes, tiles of T = 3 low
 // digits): tile.first is the index of one of the instance's (C+1)^(K-3)
-// tiles.  The workgroup stages the tile's values and arrival terms in LDS
-// (dynamic: Al [tocc + 1], Vl [J][tocc]) and backs up its occupancies with
-// the low-digit neighbours from LDS and the high-digit ones from global
-// memory: the per-state arithmetic of the direct round backup, so the same
-// bits.  Placements without room read the -inf block that ends the
-// instance's side arrays.
+// tiles.  The workgroup stages the tile's values in LDS (dynamic: Vl
+// [J][tocc]) and backs up its occupancies with the low-digit neighbours from
+// LDS, the high-digit ones and every arrival term from global memory
+// (tile_backup's AGlobal form: the staged image stays small, so more
+// workgroups share a CU): the per-state arithmetic of the direct round
+// backup, so the same bits.  Placements without room read the -inf block
+// that ends the instance's side arrays.
 template <int K, int J>
 __device__ __forceinline__ double batch_vi_tile_body(const BatchInst& I, uint32_t tb, const float* Vin,
                                                      float* Vout, const double* Ain, double* Aout,
@@ -440,13 +441,13 @@ __device__ __forceinline__ double batch_vi_tile_body(const BatchInst& I, uint32_
   const BufView aout = make_view(Aout, nocc * 8u);
   TileHigh<K, J, T> H;
   tile_high_setup<K, J, T>(M, tb, H);
-  tile_stage<J, kBlock>(M, occ, H.o0, vin, ain, Vl, Al);
+  tile_stage_values<J, kBlock>(M, occ, H.o0, vin, Vl);
   __syncthreads();
   double acc = 0.0;
   for (uint32_t i = threadIdx.x; i < occ; i += kBlock) {
     float vs[J], vn[J];
     double anew;
-    tile_backup<K, J, T, false>(M, H, occ, Vl, Al, vin, ain, i, vs, vn, anew);
+    tile_backup<K, J, T, false, true>(M, H, occ, Vl, Al, vin, ain, i, vs, vn, anew);
 #pragma unroll
     for (int e = 0; e < J; ++e) {
       st_f32(vout, vn[e], i * 4u, H.o0 * 4u + e * cls);
@@ -473,12 +474,11 @@ __global__ __launch_bounds__(kBlock) void batch_vi_tile_kernel(const BatchInst* 
   float* Vout = ((j & 1) ? V : W) + I.offset;
   const double* Ain = ((j & 1) ? A1 : A0) + I.aoff;
   double* Aout = ((j & 1) ? A0 : A1) + I.aoff;
-  double* Al = tile_lds;
-  float* Vl = reinterpret_cast<float*>(tile_lds + I.tocc + 1);
+  float* Vl = reinterpret_cast<float*>(tile_lds);   // [J][tocc]; the arrival terms stay in global memory
   double acc = 0.0;
   switch (M.K * 4 + M.J) {
 #define MDPVI_TILE_CASE(K_, J_) \
-  case K_ * 4 + J_: acc = batch_vi_tile_body<K_, J_>(I, tile.first, Vin, Vout, Ain, Aout, Al, Vl); break;
+  case K_ * 4 + J_: acc = batch_vi_tile_body<K_, J_>(I, tile.first, Vin, Vout, Ain, Aout, nullptr, Vl); break;
     MDPVI_TILE_CASE(4, 1) MDPVI_TILE_CASE(4, 2) MDPVI_TILE_CASE(4, 3)
     MDPVI_TILE_CASE(5, 1) MDPVI_TILE_CASE(5, 2) MDPVI_TILE_CASE(5, 3)
 #undef MDPVI_TILE_CASE

@@ -151,8 +151,8 @@ hipError_t launch_batch_round(const BatchInst* insts, const Tile* tiles, int n_t
                               hipStream_t s);
 // Value iteration's round in the tile form over tiles {inst, tile index} of
 // instances with tocc > 0 (K in 4..5, J <= 3 distinct sizes); lds: bytes of
-// dynamic LDS, at least (tocc + 1) * 8 + J * tocc * 4 for every listed
-// instance and at most kBatchTileLds.
+// dynamic LDS, at least J * tocc * 4 for every listed instance and at most
+// kBatchTileLds.
 hipError_t launch_batch_vi_tile(const BatchInst* insts, const Tile* tiles, int n_tiles, size_t lds, float* V,
                                 float* W, BatchCtl* ctl, int* remaining, long long j, double tol, double* A0,
                                 double* A1, hipStream_t s);

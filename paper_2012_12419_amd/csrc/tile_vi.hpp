@@ -16,7 +16,14 @@ namespace mdpvi {
 // LDS value (the block-asynchronous form; in a Jacobi sweep both are the
 // same).  Returns the new values vn, the new arrival term anew = sum_e
 // lambda_e/Lam vn_e and the values vs the backup read at the state itself.
-template <int K, int J, int T, bool SelfLatest>
+//
+// AGlobal: the arrival terms inside the tile too are read from ain (global
+// memory) instead of Al, which is then not used: the own term at o0 + i, a
+// placement along a low digit at o0 + i + size_e (C+1)^k, one without room
+// from the -inf block that follows the n_occ terms (occ entries).  The
+// workgroup then stages only the values (a smaller LDS image); the
+// arithmetic is the same.
+template <int K, int J, int T, bool SelfLatest, bool AGlobal = false>
 __device__ __forceinline__ void tile_backup(const Model& M, const TileHigh<K, J, T>& H, uint32_t occ,
                                             const float* Vl, const double* Al, BufView vin, BufView ain,
                                             uint32_t i, float (&vs)[J], float (&vn)[J], double& anew) {
@@ -50,7 +57,12 @@ __device__ __forceinline__ void tile_backup(const Model& M, const TileHigh<K, J,
       for (int e = 0; e < J; ++e) vr[T + h][e] = H.nh[h] == 0 ? vs[e] : vr[T + h][e];
     }
   }
-  const double a_rej = Al[i];
+  double a_rej;
+  if constexpr (AGlobal) {
+    a_rej = ld_f64(ain, i8, H.o0 * 8u);
+  } else {
+    a_rej = Al[i];
+  }
 #pragma unroll
   for (int k = 0; k < T; ++k) {
     const uint32_t st = static_cast<uint32_t>(M.stride[k]);
@@ -61,7 +73,13 @@ __device__ __forceinline__ void tile_backup(const Model& M, const TileHigh<K, J,
       vd[k][e] = Vl[e * occ + d];
       vr[k][e] = Vl[e * occ + r];
       const int s = M.size[e];
-      aa[k][e] = Al[n[k] + s <= M.C ? i + static_cast<uint32_t>(s) * st : occ];
+      if constexpr (AGlobal) {
+        const uint32_t nocc8 = static_cast<uint32_t>(M.n_occ) * 8u;
+        aa[k][e] = ld_f64(ain, n[k] + s <= M.C ? i8 + static_cast<uint32_t>(s) * st * 8u : nocc8 - H.o0 * 8u + i8,
+                          H.o0 * 8u);
+      } else {
+        aa[k][e] = Al[n[k] + s <= M.C ? i + static_cast<uint32_t>(s) * st : occ];
+      }
     }
   }
   const double idle = M.mu_L * static_cast<double>(M.KC - load);
@@ -83,6 +101,32 @@ __device__ __forceinline__ void tile_backup(const Model& M, const TileHigh<K, J,
     const double best = fmax(fma(M.gamma, a_rej, fma(-M.hold, fu, M.r_reject[e])), fma(M.gamma, ab, fma(-M.hold, fu, M.r_place[e])));
     vn[e] = static_cast<float>(fma(M.gamma, D, best));
     anew = fma(M.p[e], static_cast<double>(vn[e]), anew);
+  }
+}
+
+// Stages only the tile's FP32 values into Vl [J][occ] (for AGlobal
+// backups), NB threads, kStageRounds loads per thread in flight.
+template <int J, int NB>
+__device__ __forceinline__ void tile_stage_values(const Model& M, uint32_t occ, uint32_t o0, BufView vin,
+                                                  float* Vl) {
+  const uint32_t cls = static_cast<uint32_t>(M.n_occ) * 4u;
+  for (uint32_t base = 0; base < occ; base += kStageRounds * NB) {
+    float v[kStageRounds][J];
+#pragma unroll
+    for (int r = 0; r < kStageRounds; ++r) {
+      uint32_t i = base + r * NB + threadIdx.x;
+      i = i < occ ? i : occ - 1;
+#pragma unroll
+      for (int e = 0; e < J; ++e) v[r][e] = ld_f32(vin, i * 4u, o0 * 4u + e * cls);
+    }
+#pragma unroll
+    for (int r = 0; r < kStageRounds; ++r) {
+      const uint32_t i = base + r * NB + threadIdx.x;
+      if (i < occ) {
+#pragma unroll
+        for (int e = 0; e < J; ++e) Vl[e * occ + i] = v[r][e];
+      }
+    }
   }
 }
 
