@@ -378,15 +378,14 @@ int batch_round_forms(mdpvi_batch_t b, int32_t *opt);
 /* Tile form of the round kernels of operation op (0 value iteration, 1 FP64
  * evaluation) for the batch's instances of 4 or 5 hosts and up to 3 classes
  * of distinct sizes (a tuning knob: the same bits either way).  Each
- * workgroup stages one tile of (C+1)^3 occupancies in LDS (at most 60 KB;
- * value iteration: values and arrival terms of its round-form instances;
- * evaluation: values of the instances with tiles of at least 1,000
- * occupancies whose values fit 32 KB, the arrival terms of the actions then
- * coming from FP64 side arrays) and reads every neighbour along the three
- * low digits from there;
- * the other instances keep the direct round kernels.  mode 1 on, 0 off, -1
- * automatic (the default: the choice batch_autotune recorded for the
- * batch's instance shapes, else on for value iteration and off for
+ * workgroup stages the values of one tile of (C+1)^3 occupancies in LDS,
+ * reads every neighbour along the three low digits from there and the
+ * arrival terms from FP64 side arrays (value iteration: its round-form
+ * instances whose tile of values and terms would fit 60 KB; evaluation: the
+ * instances with tiles of at least 1,000 occupancies whose FP64 values fit
+ * 32 KB); the other instances keep the direct round kernels.  mode 1 on,
+ * 0 off, -1 automatic (the default: the choice batch_autotune recorded for
+ * the batch's instance shapes, else on for value iteration and off for
  * evaluation).  Errors: MDPVI_EINVAL.                                        */
 int batch_set_tile_form(mdpvi_batch_t b, int32_t op, int32_t mode);
 

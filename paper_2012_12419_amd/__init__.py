@@ -426,7 +426,9 @@ class Batch:
 
     def autotune(self, trials: int = 5, stream=None) -> dict:
         """Time the round kernels with 1, 2 and 4 occupancies per thread and
-        record the fastest per operation; returns {op: (opt, us per round)}."""
+        record the fastest per operation, then the tile forms of "vi" and
+        "eval" beside them; returns {op: (opt, us per round of the faster
+        form)}."""
         opt = (_c_int32 * 3)(0, 0, 0)
         us = (_c_double * 3)(0.0, 0.0, 0.0)
         _check(load().batch_autotune(self._h, int(trials), _stream_ptr(stream), opt, us))
