@@ -136,8 +136,14 @@ def test_batch_round_forms_bit_identical_and_tuned(mdpvi, case):
         assert opt in (1, 2, 4) and us > 0, (op, opt, us)
     other = mdpvi.Batch(insts)
     assert other.round_forms() == {op: rec[op][0] for op in rec}
+    # the tile forms' choices recorded for these shapes reach a new batch too
+    for op in ("vi", "eval"):
+        b.set_tile_form(op, -1)
+        assert other.tile_form_instances(op) == b.tile_form_instances(op), op
     with pytest.raises(mdpvi.MdpviError):
         other.set_round_form("vi", 3)
+    with pytest.raises(mdpvi.MdpviError):
+        other.set_tile_form("adjoint", 1)
 
 
 def test_batch_tile_forms_bit_identical(mdpvi):
